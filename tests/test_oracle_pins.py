@@ -1,0 +1,601 @@
+"""Pins of the reference oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, values printed in the paper (tests/golden), invariants, special cases
+that reduce to textbook results, and brute force.  None of these needs a GPU.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(20260207)
+
+
+def _rand_points(n, a, rlo=1.8, rhi=30.0):
+    r = RNG.uniform(rlo, rhi, n)
+    th = RNG.uniform(0.15, np.pi - 0.15, n)
+    return r, th
+
+
+# ------------------------------------------------------------------ metric
+@pytest.mark.parametrize("a", [0.0, 0.7, 0.9, 0.99])
+def test_metric_inverse_and_determinant(a):
+    """App. A: gamma^ij is the inverse of gamma_ij and det = rho^4 xi sin^2."""
+    for r, th in zip(*_rand_points(20, a)):
+        m = O.metric(a, r, th)
+        g = np.array([[m[2], 0, m[5]], [0, m[3], 0], [m[5], 0, m[4]]])
+        gi = np.array([[m[6], 0, m[9]], [0, m[7], 0], [m[9], 0, m[8]]])
+        assert np.allclose(g @ gi, np.eye(3), atol=1e-13, rtol=0)
+        rho2 = r * r + a * a * np.cos(th) ** 2
+        xi = 1 + 2 * r / rho2
+        assert np.isclose(np.linalg.det(g), rho2 ** 2 * xi * np.sin(th) ** 2, rtol=1e-12)
+        assert np.isclose(m[10] ** 2, np.linalg.det(g), rtol=1e-12)
+        # lapse / shift from the 4-metric: g_00 = -alpha^2 + beta_r beta^r
+        # and beta_r = gamma_rr beta^r = 2r/rho^2 (Kerr-Schild g_0r)
+        assert np.isclose(m[2] * m[1], 2 * r / rho2, rtol=1e-13)
+
+
+def test_metric_schwarzschild_limit():
+    """a -> 0: diagonal Kerr-Schild Schwarzschild metric (App. A, last line)."""
+    for r, th in zip(*_rand_points(10, 0.0)):
+        m = O.metric(0.0, r, th)
+        s2 = np.sin(th) ** 2
+        assert np.allclose(m[[2, 3, 4, 5]], [1 + 2 / r, r * r, r * r * s2, 0.0], rtol=1e-14, atol=0)
+        assert np.isclose(m[0], 1 / np.sqrt(1 + 2 / r), rtol=1e-14)
+        assert np.isclose(m[1], 2 / (r + 2), rtol=1e-14)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9, 0.99])
+def test_metric_derivatives_match_finite_differences(a):
+    """Analytic d_r, d_theta of alpha, beta^r, gamma^ij (Sec. 2.2) vs central
+    differences of the metric itself."""
+    idx = [0, 1, 6, 7, 8, 9]
+    for r, th in zip(*_rand_points(15, a)):
+        d = O.metric_deriv(a, r, th)
+        h = 2e-6
+        for n, i in enumerate(idx):
+            fr = (O.metric(a, r + h, th)[i] - O.metric(a, r - h, th)[i]) / (2 * h)
+            ft = (O.metric(a, r, th + h)[i] - O.metric(a, r, th - h)[i]) / (2 * h)
+            sc = max(1.0, abs(O.metric(a, r, th)[i]), abs(d[2 * n]), abs(d[2 * n + 1]))
+            assert abs(d[2 * n] - fr) < 1e-8 * sc
+            assert abs(d[2 * n + 1] - ft) < 1e-8 * sc
+
+
+# --------------------------------------------------------- equations of motion
+def _grad(fun, z, h=1e-6):
+    g = np.zeros(6)
+    for i in range(6):
+        zp, zm = z.copy(), z.copy()
+        zp[i] += h
+        zm[i] -= h
+        g[i] = (fun(zp) - fun(zm)) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9, 0.995])
+def test_neutral_rhs_is_hamiltonian_flow(a):
+    """eqs. p1/p2: (dx/dt, du/dt) = (dH/du, -dH/dx) with H of eq. Ham (q=0)."""
+    for _ in range(10):
+        z = np.array([RNG.uniform(2, 20), RNG.uniform(0.2, 2.9), RNG.uniform(0, 6),
+                      RNG.normal(), RNG.normal() * 2, RNG.normal() * 3])
+        f = O.rhs(a, 0.0, z)
+        g = _grad(lambda y: O.energy(a, y), z)
+        assert np.allclose(f, np.r_[g[3:], -g[:3]], atol=2e-8, rtol=0)
+
+
+@pytest.mark.parametrize("qm", [1.0, -1.0])
+@pytest.mark.parametrize("a", [0.0, 0.7, 0.9])
+def test_charged_wald_conserves_H_and_L(a, qm):
+    """Sec. 3.1.3: in the Wald field H = -u_0 - (q/m) A_0 and
+    L = u_phi + (q/m) A_phi are constants of the motion: their gradients are
+    orthogonal to the flow F of eqs. p1-O2."""
+    B0 = 2.0
+    H = lambda y: O.energy(a, y) - qm * O.wald_potential(a, B0, y[0], y[1])[0]
+    L = lambda y: y[5] + qm * O.wald_potential(a, B0, y[0], y[1])[3]
+    for _ in range(8):
+        z = np.array([RNG.uniform(2, 12), RNG.uniform(0.3, 2.8), 0.4,
+                      RNG.normal(), RNG.normal(), RNG.normal() * 2])
+        D, B = O.wald_fields(a, B0, z[0], z[1])
+        f = O.rhs(a, qm, z, D, B)
+        gH, gL = _grad(H, z), _grad(L, z)
+        assert abs(gH @ f) < 1e-8 * max(np.abs(f).max() * np.abs(gH).max(), 1)
+        assert abs(gL @ f) < 1e-8 * max(np.abs(f).max() * np.abs(gL).max(), 1)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9, 0.99])
+def test_wald_field_is_curl_of_potential(a):
+    """App. B.1: B^i = eta^ijk d_j A_k / sqrt(g); E_i = d_i A_0; E_phi = 0,
+    with E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei)."""
+    B0, h = 1.3, 1e-6
+    for r, th in zip(*_rand_points(10, a, 1.6, 15)):
+        D, B = O.wald_fields(a, B0, r, th)
+        A = lambda rr, tt: O.wald_potential(a, B0, rr, tt)
+        dA_r = (A(r + h, th) - A(r - h, th)) / (2 * h)
+        dA_t = (A(r, th + h) - A(r, th - h)) / (2 * h)
+        m = O.metric(a, r, th)
+        sg = m[10]
+        assert np.isclose(B[0], dA_t[3] / sg, rtol=1e-7, atol=1e-9)
+        assert np.isclose(B[1], -dA_r[3] / sg, rtol=1e-7, atol=1e-9)
+        assert np.isclose(B[2], -dA_t[1] / sg, rtol=1e-7, atol=1e-9)
+        Dl = np.array([[m[2], 0, m[5]], [0, m[3], 0], [m[5], 0, m[4]]]) @ D
+        E = m[0] * Dl + sg * m[1] * np.array([0.0, -B[2], B[1]])
+        assert np.allclose(E, [dA_r[0], dA_t[0], 0.0], rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9, 0.99])
+def test_circular_orbits_are_equilibria(a):
+    """Prograde equatorial circular orbits (Bardeen-Press-Teukolsky closed
+    forms) with the Kerr-Schild u_r = (2rE - aL)/Delta are fixed points of
+    the radial motion, rotate at Omega = 1/(r^1.5 + a) and have H = E."""
+    for r in (8.0, 15.0, 40.0):
+        Dn = r ** 0.75 * np.sqrt(r ** 1.5 - 3 * r ** 0.5 + 2 * a)
+        E = (r ** 1.5 - 2 * r ** 0.5 + a) / Dn
+        L = (r * r - 2 * a * r ** 0.5 + a * a) / Dn
+        z = np.array([r, np.pi / 2, 0.0, (2 * r * E - a * L) / (r * r - 2 * r + a * a), 0.0, L])
+        f = O.rhs(a, 0.0, z)
+        assert abs(f[0]) < 1e-14 and abs(f[3]) < 1e-14 and abs(f[4]) < 1e-14
+        assert np.isclose(f[2], 1 / (r ** 1.5 + a), rtol=1e-13)
+        assert np.isclose(O.energy(a, z), E, rtol=1e-14)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, 0.9])
+def test_isco_marks_radial_stability(a):
+    """The radial motion at fixed u_phi is a one-degree-of-freedom
+    Hamiltonian flow; its linearisation about a circular orbit has
+    det(J) > 0 (stable) outside the ISCO and < 0 inside (BPT r_isco)."""
+    Z1 = 1 + (1 - a * a) ** (1 / 3) * ((1 + a) ** (1 / 3) + (1 - a) ** (1 / 3))
+    Z2 = np.sqrt(3 * a * a + Z1 * Z1)
+    risco = 3 + Z2 - np.sqrt((3 - Z1) * (3 + Z1 + 2 * Z2))
+
+    def detJ(r):
+        Dn = r ** 0.75 * np.sqrt(r ** 1.5 - 3 * r ** 0.5 + 2 * a)
+        E = (r ** 1.5 - 2 * r ** 0.5 + a) / Dn
+        L = (r * r - 2 * a * r ** 0.5 + a * a) / Dn
+        z = np.array([r, np.pi / 2, 0.0, (2 * r * E - a * L) / (r * r - 2 * r + a * a), 0.0, L])
+        J = np.zeros((2, 2))
+        for col, i in enumerate((0, 3)):
+            h = 1e-6
+            zp, zm = z.copy(), z.copy()
+            zp[i] += h
+            zm[i] -= h
+            d = (O.rhs(a, 0, zp) - O.rhs(a, 0, zm)) / (2 * h)
+            J[:, col] = d[[0, 3]]
+        return np.linalg.det(J)
+
+    assert detJ(risco * 1.02) > 0
+    assert detJ(risco * 0.98) < 0
+
+
+def _table_rows():
+    rows = []
+    with open(os.path.join(GOLD, "table1_neutral.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, a, E, r0, ur, uph = line.split()
+                rows.append((name, float(a), float(E), float(r0), float(ur), float(uph)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _table_rows(), ids=lambda r: r[0])
+def test_table1_neutral_initial_energy(row):
+    """Table tab:params (App. C): H(z^0) reproduces the printed E to the
+    table's printed precision."""
+    name, a, E, r0, ur, uph = row
+    z = [r0, np.pi / 2, 0.0, ur, 0.0, uph]
+    assert abs(O.energy(a, z) / E - 1) < 5e-9
+
+
+def test_table1_rka8_angular_momentum():
+    """Table tab:params RKA8 row: L = u_phi + (q/m) A_phi (Sec. 3.1.3, with
+    the factor B0) equals the printed 5.0."""
+    with open(os.path.join(GOLD, "table1_charged.txt")) as f:
+        line = [l for l in f if l.strip() and not l.startswith("#")][0].split()
+    a, B0, E, L, r0, th0, ur, ut, up = map(float, line[1:])
+    A = O.wald_potential(a, B0, r0, th0)
+    assert abs(up + A[3] - L) < 5e-5
+
+
+# ------------------------------------------------------------------ pushers
+ORBIT = (0.995, np.array([10.021533, np.pi / 2, 0.0, 0.201211, 0.0, 2.0]))
+ORBIT2 = (0.995, np.array([4.376281, np.pi / 2, 0.0, 0.487625, 0.0, 1.82]))
+
+
+def _evolve(stepfun, z, n):
+    for _ in range(n):
+        z = stepfun(z)
+    return z
+
+
+def test_rk4_is_fourth_order():
+    """Sec. 2.2.1: global error of RK4 falls by 2^4 when dt halves."""
+    a, z0 = ORBIT
+    T = 8.0
+
+    def run(dt):
+        P = O.push_params(a, dt)
+        return _evolve(lambda z: O.step_rk4(P, 0.0, z)[0], z0.copy(), int(round(T / dt)))
+
+    ref = run(0.0125)
+    e1 = np.abs(run(0.2) - ref).max()
+    e2 = np.abs(run(0.1) - ref).max()
+    assert 12 < e1 / e2 < 20
+
+
+def test_imr_second_order_and_time_reversible():
+    """Sec. 2.2.2: the implicit midpoint rule is second order and symmetric."""
+    a, z0 = ORBIT
+    T = 8.0
+
+    def run(dt):
+        P = O.push_params(a, dt, tol=1e-15, kmax=200)
+        return _evolve(lambda z: O.step_imr(P, 0.0, z)[0], z0.copy(), int(round(T / dt)))
+
+    ref = run(0.0125)
+    e1 = np.abs(run(0.2) - ref).max()
+    e2 = np.abs(run(0.1) - ref).max()
+    assert 3.5 < e1 / e2 < 4.5
+    P = O.push_params(a, 0.1, tol=1e-15, kmax=200)
+    Pb = O.push_params(a, -0.1, tol=1e-15, kmax=200)
+    z1 = O.step_imr(P, 0.0, z0)[0]
+    zb = O.step_imr(Pb, 0.0, z1)[0]
+    assert np.abs(zb - z0).max() < 1e-12
+
+
+def test_imr_fixed_point_independent_of_guess():
+    """Any starting guess converges to the same IMR solution (the property
+    the learned guess relies on)."""
+    a, z0 = ORBIT2
+    P = O.push_params(a, 0.1, tol=1e-14, kmax=100)
+    z_plain, k1, _ = O.step_imr(P, 0.0, z0)
+    z_rk4 = O.step_rk4(P, 0.0, z0)[0]
+    z_g, k2, _ = O.step_imr(P, 0.0, z0, guess=z_rk4)
+    assert np.abs(z_plain - z_g).max() < 1e-13
+    assert 0 < k2 < k1
+
+
+def test_hamiltonian_scheme_conserves_energy_exactly():
+    """Sec. 2.2.3 / App. D: the discrete-gradient scheme conserves H to
+    round-off and keeps u_phi exactly constant (strong-field orbit a.995_2
+    at the paper's dt = 0.1)."""
+    a, z0 = ORBIT2
+    # 1e-13: the rounding floor of the difference quotients at dt = 0.1
+    P = O.push_params(a, 0.1, tol=1e-13, kmax=100)
+    H0 = O.energy(a, z0)
+    z = z0.copy()
+    worst = 0.0
+    for _ in range(400):
+        z, k = O.step_ham(P, z)
+        assert k > 0
+        assert z[5] == z0[5]
+        worst = max(worst, abs(O.energy(a, z) / H0 - 1))
+    assert worst < 5e-14
+    # RK4 at the same dt violates it by orders of magnitude more
+    z = z0.copy()
+    worst_rk = 0.0
+    for _ in range(400):
+        z = O.step_rk4(P, 0.0, z)[0]
+        worst_rk = max(worst_rk, abs(O.energy(a, z) / H0 - 1))
+    assert worst_rk > 1e3 * worst
+
+
+def test_hamiltonian_scheme_second_order_and_reversible():
+    a, z0 = ORBIT
+    T = 8.0
+
+    def run(dt):
+        P = O.push_params(a, dt, tol=1e-13, kmax=200)
+        return _evolve(lambda z: O.step_ham(P, z)[0], z0.copy(), int(round(T / dt)))
+
+    ref = run(0.0125)
+    e1 = np.abs(run(0.2) - ref).max()
+    e2 = np.abs(run(0.1) - ref).max()
+    assert 3.3 < e1 / e2 < 4.7
+    P = O.push_params(a, 0.1, tol=1e-13, kmax=200)
+    Pb = O.push_params(a, -0.1, tol=1e-13, kmax=200)
+    z1 = O.step_ham(P, z0)[0]
+    assert np.abs(O.step_ham(Pb, z1)[0] - z0).max() < 1e-12
+
+
+def _c1_particles(n=64):
+    return O.init_particles(O.INIT_ORBITS, 0.0, 7, n, 6.0, 20.0, np.pi / 4, 3 * np.pi / 4, 0.1)
+
+
+@pytest.mark.parametrize("pusher,implicit", [(O.HYB1, O.HAM), (O.HYB2, O.HAM)])
+def test_hybrid_threshold_limits_neutral(pusher, implicit):
+    """The hybrid with an infinite threshold is RK4 and with a zero
+    threshold is the implicit scheme, bit for bit."""
+    base = _c1_particles()
+    for thr, ref_pusher in ((np.inf, O.RK4), (-np.inf, implicit)):
+        p1, p2 = base.copy(), base.copy()
+        O.push(O.push_params(0.0, 0.05, pusher=pusher, thr=thr, r_min=2.0), p1)
+        O.push(O.push_params(0.0, 0.05, pusher=ref_pusher, r_min=2.0), p2)
+        assert np.array_equal(p1.state(), p2.state())
+
+
+def test_hybrid_threshold_limits_charged():
+    a, B0 = 0.9, 1.0
+    base = O.init_particles(O.INIT_SHELL_ISO, a, 3, 64, 2.0, 10.0, 0.3, 2.8, 1.0)
+    for thr, ref_pusher in ((np.inf, O.RK4), (-np.inf, O.IMR)):
+        p1, p2 = base.copy(), base.copy()
+        kw = dict(field_kind=O.FIELDS_WALD, B0=B0, r_min=1.44)
+        O.push(O.push_params(a, 0.05, pusher=O.HYB2, thr=thr, **kw), p1)
+        O.push(O.push_params(a, 0.05, pusher=ref_pusher, **kw), p2)
+        assert np.array_equal(p1.state(), p2.state())
+
+
+def test_hyb2_bounds_energy_violation():
+    """Sec. 3.1.2: Hyb2 keeps |H - H0|/H0 below its threshold while RK4 alone
+    exceeds it (a.995_2, dt = 0.05, threshold 1e-12 as in Table 2)."""
+    a, z0 = ORBIT2
+    thr = 1e-12
+    p = O.Particles.from_state(z0, 0.0)
+    p.H0[:] = O.energy(a, z0)
+    q = p.copy()
+    Ph = O.push_params(a, 0.05, pusher=O.HYB2, thr=thr, tol=1e-13, kmax=200)
+    Pr = O.push_params(a, 0.05)
+    worst_h = worst_r = 0.0
+    n_impl = 0
+    for _ in range(600):
+        O.push(Ph, p)
+        O.push(Pr, q)
+        n_impl += int(p.flags[0] & O.IMPLICIT != 0)
+        worst_h = max(worst_h, abs(O.energy(a, p.state()[0]) / p.H0[0] - 1))
+        worst_r = max(worst_r, abs(O.energy(a, q.state()[0]) / p.H0[0] - 1))
+    # below the threshold up to the implicit scheme's own round-off drift
+    assert worst_h < thr + 1e-14
+    assert worst_r > thr
+    assert 0 < n_impl < 600
+
+
+def test_charged_energy_budget_residual_is_rk4_local_error():
+    """The charged switch quantity |e' - e - W|/|e| (reading for grid fields)
+    falls like dt^5 for RK4 on a smooth field."""
+    a, B0 = 0.9, 1.0
+    z0 = np.array([5.0, 1.2, 0.0, 0.3, 0.4, 1.5])
+    vals = []
+    for dt in (0.04, 0.02):
+        P = O.push_params(a, dt, field_kind=O.FIELDS_WALD, B0=B0)
+        z1, W = O.step_rk4(P, 1.0, z0)
+        e0 = O.energy(a, z0)
+        vals.append(abs(O.energy(a, z1) - e0 - W) / abs(e0))
+    assert 20 < vals[0] / vals[1] < 45
+
+
+# ----------------------------------------------------------------- gather
+def test_gather_exact_for_bilinear_densitized_fields():
+    """The metric-weighted bilinear gather reproduces exactly any field
+    whose sqrt(g) F is bilinear in (r, theta) on its sub-grid."""
+    g = O.Grid(0.9, 12, 10, 1.3, 15.0)
+    coef = RNG.normal(size=(6, 4))
+    G = []
+    for c in range(6):
+        nT, nR = g.shape(c)
+        R = (g.rh if c in (0, 4, 5) else g.rn)[:nR]
+        T = (g.th if c in (1, 3, 5) else g.tn)[:nT]
+        k = coef[c]
+        G.append(k[0] + k[1] * R[None, :] + k[2] * T[:, None] + k[3] * R[None, :] * T[:, None])
+    for _ in range(30):
+        r, th = RNG.uniform(2.0, 13.0), RNG.uniform(0.4, 2.7)
+        D, B = O.gather(g, G, r, th)
+        sg = O.metric(0.9, r, th)[10]
+        for c in range(6):
+            k = coef[c]
+            want = (k[0] + k[1] * r + k[2] * th + k[3] * r * th) / sg
+            got = (D if c < 3 else B)[c % 3]
+            assert abs(got - want) < 1e-12 * max(1, abs(want))
+
+
+# ---------------------------------------------------------------- deposit
+def test_deposit_weights_partition_and_flat_cic():
+    """eqs. v1-v5: weights sum to one; with sqrt(g) = 1 they are the
+    bilinear (cloud-in-cell) weights."""
+    g = O.Grid(0.9, 10, 10, 1.3, 15.0)
+    for _ in range(20):
+        p, q = RNG.integers(0, 10), RNG.integers(0, 10)
+        fr, ft = RNG.uniform(), RNG.uniform()
+        r = g.rn[p] + fr * (g.rn[p + 1] - g.rn[p])
+        th = g.tn[q] + ft * (g.tn[q + 1] - g.tn[q])
+        W = O.dep_weights(g, r, th, int(p), int(q))
+        assert abs(W.sum() - 1) < 1e-14 and (W >= 0).all()
+        Wf = O.dep_weights(g, r, th, int(p), int(q), flat=True)
+        fr = (r - g.rn[p]) / (g.rn[p + 1] - g.rn[p])
+        ft = (th - g.tn[q]) / (g.tn[q + 1] - g.tn[q])
+        cic = [(1 - fr) * (1 - ft), fr * (1 - ft), (1 - fr) * ft, fr * ft]
+        assert np.allclose(Wf, cic, atol=1e-14, rtol=0)
+
+
+def test_deposit_weights_converge_to_exact_subvolumes():
+    """Brute force: the 4x4-point trapezoid sub-volumes agree with adaptive
+    quadrature of sqrt(gamma) over the four sub-rectangles."""
+    a = 0.99
+    g = O.Grid(a, 6, 6, 1.03, 6.0)
+    sg = lambda t, r: O.metric(a, r, t)[10]
+    for (p, q) in ((0, 0), (2, 3), (5, 2)):
+        r = g.rn[p] + 0.3 * (g.rn[p + 1] - g.rn[p])
+        th = g.tn[q] + 0.7 * (g.tn[q + 1] - g.tn[q])
+        W = O.dep_weights(g, r, th, p, q)
+        V = lambda r0, r1, t0, t1: integrate.dblquad(sg, r0, r1, t0, t1, epsabs=1e-13)[0]
+        ra, rb, ta, tb = g.rn[p], g.rn[p + 1], g.tn[q], g.tn[q + 1]
+        Vs = np.array([V(r, rb, th, tb), V(ra, r, th, tb), V(r, rb, ta, th), V(ra, r, ta, th)])
+        assert np.allclose(W, Vs / Vs.sum(), atol=3e-3, rtol=0)
+
+
+def _lengths(g):
+    Lr = np.r_[g.rh[0] - g.rn[0], np.diff(g.rh), g.rn[-1] - g.rh[-1]]
+    dth = g.tn[1] - g.tn[0]
+    Lt = np.r_[0.5 * dth, np.full(g.nth - 1, dth), 0.5 * dth]
+    return Lr, Lt
+
+
+def test_deposit_discrete_continuity_and_total_charge():
+    """The deposited rho and J satisfy the discrete continuity equation to
+    round-off at every node, also for moves that cross several cells, and
+    the total deposited charge equals the total particle charge."""
+    g = O.Grid(0.9, 16, 12, 1.3, 20.0)
+    n = 500
+    old = np.c_[RNG.uniform(2, 18, n), RNG.uniform(0.1, 3.0, n), RNG.uniform(0, 6, n)]
+    new = old + np.c_[RNG.uniform(-1.5, 1.5, n), RNG.uniform(-0.3, 0.3, n), RNG.uniform(-1, 1, n)]
+    new[:, 0] = np.clip(new[:, 0], 1.31, 19.9)
+    new[:, 1] = np.clip(new[:, 1], g.th0 + 1e-9, np.pi - g.th0 - 1e-9)
+    qw = RNG.choice([-1.0, 1.0], n) * RNG.uniform(0.5, 2, n)
+    dt = 0.5
+    rho0 = O.deposit(g, dt, old, old, qw)[0]
+    rho1, Jr, Jt, Jp = O.deposit(g, dt, old, new, qw)
+    Lr, Lt = _lengths(g)
+    res = (rho1 - rho0) / dt
+    # divergence of the densitized current with dual lengths; the edge
+    # fluxes outside the grid are zero
+    Jr_p = np.zeros((g.nth + 1, g.nr + 2))
+    Jr_p[:, 1:-1] = Jr
+    Jt_p = np.zeros((g.nth + 2, g.nr + 1))
+    Jt_p[1:-1, :] = Jt
+    res += (Jr_p[:, 1:] - Jr_p[:, :-1]) / Lr[None, :]
+    res += (Jt_p[1:, :] - Jt_p[:-1, :]) / Lt[:, None]
+    assert np.abs(res).max() < 1e-12 * np.abs(rho1).max() / dt
+    Q = (rho1 * 2 * np.pi * Lr[None, :] * Lt[:, None]).sum()
+    assert abs(Q - qw.sum()) < 1e-12 * np.abs(qw).sum()
+
+
+# ------------------------------------------------------------------ Maxwell
+def _rplus(a):
+    return 1 + np.sqrt(1 - a * a)
+
+
+def test_fdtd_preserves_divB_and_gauss_with_particles():
+    """Yee staggering keeps div B constant (Sec. 2.1); with the conserving
+    current the Gauss residual of the integer chain stays constant too."""
+    a = 0.9
+    g = O.Grid(a, 20, 20, 0.9 * _rplus(a), 12.0)
+    D, B = O.wald_grid(g, 1.0)
+    F = O.Fields.uniform_levels(g, D, B)
+    dt = 0.2 * min(np.diff(g.rn).min(), g.rn[0] * (g.tn[1] - g.tn[0]))
+    P = O.push_params(a, dt, field_kind=O.FIELDS_GRID, r_min=_rplus(a), r_max=12.0,
+                      th_lo=g.th0, th_hi=np.pi - g.th0)
+    p = O.init_particles(O.INIT_SHELL_MJ, a, 5, 1000, 2.5, 10.0, 0.2, 2.9, 0.3, w=0.05)
+    st = p.state()
+    F.rho[:] = O.deposit(g, dt, st[:, :3], st[:, :3], p.qm * p.w)[0]
+    G0, dB0 = O.gauss_residual(g, F.Dn, F.rho), O.div_B(g, F.Bn)
+    for _ in range(15):
+        O.pic_step(P, g, F, p)
+    G1, dB1 = O.gauss_residual(g, F.Dn, F.rho), O.div_B(g, F.Bn)
+    assert np.abs(dB1 - dB0).max() < 1e-11 * np.abs(dB0).max()
+    assert np.abs(G1 - G0).max() < 1e-11 * max(np.abs(G0).max(), np.abs(F.rho).max())
+
+
+def test_kerr_wald_is_stationary_to_second_order():
+    """The Kerr Wald field (App. B.1, E_theta reading) is an exact stationary
+    vacuum solution: outside the horizon it stays put to O(h^2)."""
+    a, T = 0.9, 2.0
+    errs = []
+    for N in (24, 48):
+        g = O.Grid(a, N, N, 0.9 * _rplus(a), 12.0)
+        D, B = O.wald_grid(g, 1.0)
+        F = O.Fields.uniform_levels(g, D, B)
+        dt0 = 0.3 * min(np.diff(g.rn).min(), g.rn[0] * (g.tn[1] - g.tn[0]))
+        steps = int(np.ceil(T / dt0))
+        P = O.push_params(a, T / steps)
+        for _ in range(steps):
+            O.pic_step(P, g, F, None)
+        e = []
+        for lev, ref, cs in ((F.Bn, B, (3, 4, 5)), (F.Dn, D, (0, 1, 2))):
+            for k, c in enumerate(cs):
+                nT, nR = g.shape(c)
+                R = (g.rh if c in (0, 4, 5) else g.rn)[:nR]
+                Th = (g.th if c in (1, 3, 5) else g.tn)[:nT]
+                mk = (R[None] > 3) & (R[None] < 7) & (Th[:, None] > 0.4) & (Th[:, None] < np.pi - 0.4)
+                e.append(np.abs(lev[k] - ref[k])[mk].max() / np.abs(ref[k][mk]).max())
+        errs.append(np.array(e))
+    assert (errs[0] < 1e-2).all()
+    assert (errs[0] / errs[1] > 3.0).all()
+
+
+def test_split_monopole_divergence_free():
+    g = O.Grid(0.9, 32, 32, 1.29, 20.0)
+    D, B = O.split_monopole_grid(g, 1.0, 1e3)
+    assert np.abs(O.div_B(g, B)).max() < 1e-12 * np.abs(g.densitize(3, B[0])).max()
+    # far from the sheet, B^r -> 4 B0 sin(theta)/sqrt(g) (monopole of Psi)
+    j = 3
+    sg = np.array([O.metric(0.9, g.rn[i], g.th[j])[10] for i in range(g.nr + 1)])
+    assert np.allclose(B[0][j] * sg, -4 * np.sin(g.th[j]), rtol=2e-3)
+
+
+def test_poynting_vanishes_for_static_schwarzschild_wald():
+    """a = 0 Wald vacuum carries no energy flux: P_BZ -> 0 with resolution."""
+    vals = []
+    for N in (16, 32):
+        g = O.Grid(0.0, N, N, 1.8, 12.0)
+        D, B = O.wald_grid(g, 1.0)
+        vals.append(np.abs(O.poynting(g, D, B)[N // 2]))
+    assert vals[1] < vals[0] / 3 or vals[1] < 1e-14
+
+
+# ------------------------------------------------------------ initial data
+def test_splitmix64_reference_outputs():
+    """The counter-based generator is SplitMix64: from state 0 it yields the
+    generator's published first outputs (top 53 bits)."""
+    with open(os.path.join(GOLD, "splitmix64_seed0.txt")) as f:
+        vals = [int(l, 16) for l in f if l.strip() and not l.startswith("#")]
+    for k, v in enumerate(vals):
+        assert int(O.uniform(0, k) * 2 ** 53) == v >> 11
+
+
+def test_shell_sampling_is_uniform_in_proper_volume():
+    """Positions follow sqrt(gamma) dr dtheta (proper volume): the share of
+    particles below r_mid matches the volume ratio from quadrature."""
+    a, r0, r1, t0, t1 = 0.9, 2.0, 30.0, np.pi / 200, np.pi - np.pi / 200
+    n = 40000
+    p = O.init_particles(O.INIT_SHELL_ISO, a, 11, n, r0, r1, t0, t1, 1.0)
+    sg = lambda t, r: O.metric(a, r, t)[10]
+    for rm in (5.0, 12.0):
+        frac = integrate.dblquad(sg, r0, rm, t0, t1)[0] / integrate.dblquad(sg, r0, r1, t0, t1)[0]
+        got = (p.r < rm).mean()
+        assert abs(got - frac) < 4 * np.sqrt(frac * (1 - frac) / n)
+    tm = 0.8
+    frac = integrate.dblquad(sg, r0, r1, t0, tm)[0] / integrate.dblquad(sg, r0, r1, t0, t1)[0]
+    assert abs((p.th < tm).mean() - frac) < 4 * np.sqrt(frac * (1 - frac) / n)
+    # |u| uniform on [0, 1] in the FIDO frame: Gamma = sqrt(1 + |u|^2)
+    m = np.array([O.metric(a, r, t) for r, t in zip(p.r[:2000], p.th[:2000])])
+    u2 = (m[:, 6] * p.ur[:2000] ** 2 + m[:, 7] * p.uth[:2000] ** 2 + m[:, 8] * p.uph[:2000] ** 2
+          + 2 * m[:, 9] * p.ur[:2000] * p.uph[:2000])
+    assert abs(np.sqrt(u2).mean() - 0.5) < 0.02
+    assert set(np.unique(p.qm)) == {-1.0, 1.0}
+
+
+def test_maxwell_juettner_mean_lorentz_factor():
+    """Maxwell-Juettner at Theta: <gamma> = K1(1/Theta)/K2(1/Theta) + 3 Theta."""
+    a, theta, n = 0.99, 0.1, 40000
+    p = O.init_particles(O.INIT_SHELL_MJ, a, 5, n, 1.2, 18.0, 0.1, 3.0, theta)
+    m = np.array([O.metric(a, r, t) for r, t in zip(p.r, p.th)])
+    u2 = (m[:, 6] * p.ur ** 2 + m[:, 7] * p.uth ** 2 + m[:, 8] * p.uph ** 2
+          + 2 * m[:, 9] * p.ur * p.uph)
+    gam = np.sqrt(1 + u2)
+    want = special.kn(1, 1 / theta) / special.kn(2, 1 / theta) + 3 * theta
+    assert abs(gam.mean() - want) < 4 * gam.std() / np.sqrt(n)
+    # pairs share their position and carry opposite charge
+    assert np.array_equal(p.r[0::2], p.r[1::2])
+    assert (p.qm[0::2] == 1).all() and (p.qm[1::2] == -1).all()
+
+
+# ---------------------------------------------------------------------- MLP
+def test_mlp_gradient_matches_finite_differences():
+    """Backward pass of the guess network vs central differences of its
+    FP64 loss."""
+    theta = RNG.normal(size=O.NPARAM) * 0.2
+    X = RNG.normal(size=(7, 14))
+    T = RNG.normal(size=(7, 6))
+    loss, g = O.mlp_loss_grad(theta, X, T)
+    idx = RNG.choice(O.NPARAM, 60, replace=False)
+    for i in idx:
+        h = 1e-6
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (O.mlp_loss_grad(tp, X, T)[0] - O.mlp_loss_grad(tm, X, T)[0]) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 * max(1, abs(fd))
+    Y = O.mlp_forward(theta, X)
+    assert np.isclose(((Y - T) ** 2).mean(), loss, rtol=1e-14)
