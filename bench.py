@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Throughput of the GRPIC hot path on one MI355X.
+
+A step is one full pass of the method over the particles: for the default
+workload (the full PIC cycle) the Maxwell sub-steps 1-4, field gather and
+hybrid push, deposit, and sub-steps 7-10.  Prints one JSON line with the
+particle-steps/s of the whole job, the roofline of the dominant kernel (from
+HIP-event timings taken by the library on its own stream) and the CPU oracle
+timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SEED = 2602074520
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 FLOP/clk)
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+
+# Algorithmic FP64 operations per particle, counted on the formulas the push
+# evaluates (+, -, *, / and sqrt = 1; fused a*b+c = 2; sin, cos, log = 1).
+FLOP_METRIC_D = 89     # metric + derivatives of alpha, beta^r, gamma^ij
+FLOP_GATHER = 76       # cell location + 6 metric-weighted bilinear reads
+FLOP_RHS = 93          # Gamma, dx/dt, gravity + Lorentz acceleration, power
+FLOP_ENERGY = 43       # e = alpha Gamma - beta^r u_r at one state
+FLOP_RK4_COMB = 90     # stage states and the weighted sum
+FLOP_IMR_EXTRA = 42    # midpoint state, update, convergence test
+FLOP_WEIGHTS = 610     # 7 x 7 sqrt(gamma) samples, trapezoid sub-volumes, cell
+FLOP_EVAL = FLOP_METRIC_D + FLOP_GATHER + FLOP_RHS
+FLOP_RK4 = 4 * FLOP_EVAL + FLOP_RK4_COMB
+FLOP_SWITCH = 2 * FLOP_ENERGY + 4
+FLOP_IMR_ITER = FLOP_EVAL + FLOP_IMR_EXTRA
+# algorithmic HBM bytes per particle of the explicit push pass: state in/out
+# (2 x 48), q/m, flags, H0, herr in/out, iterations, old position + dphi,
+# new weights + cell
+BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 32 + 4
+# deposit per particle: old/new weights and cells, q/m, w, dphi, flags
+BYTES_DEPOSIT = 32 + 32 + 4 + 4 + 1 + 8 + 8 + 1
+
+
+def rplus(a):
+    return 1.0 + np.sqrt(1.0 - a * a)
+
+
+WORKLOADS = {
+    "c3": dict(
+        desc=("full PIC cycle, plasma-filled Wald magnetosphere: Kerr a=0.99, "
+              "1024x1024 (r,theta) grid r in [0.9 r+, 20], absorbing layer from 18, "
+              "2^24 e+/e- macro-particles uniform in proper volume, Maxwell-Juettner "
+              "Theta=0.1, FDTD + gather + Hyb2 push (RK4 -> IMR) + conserving deposit"),
+        a=0.99, nr=1024, nth=1024, r_out=20.0, n=1 << 24, mode="evolve",
+        pusher="hyb2", thr=1e-13, theta=0.1, r_abs=18.0),
+    "c2": dict(
+        desc=("charged test particles in the Kerr a=0.9 Wald field (B0=1) on a "
+              "512x512 grid, r in [0.9 r+, 50]: 2^20 particles, q/m=+-1, |u|~U[0,1] "
+              "isotropic, gather + Hyb2 push (RK4 -> IMR), dt=0.01, no deposit"),
+        a=0.9, nr=512, nth=512, r_out=50.0, n=1 << 20, mode="static",
+        pusher="hyb2", thr=1e-13, theta=1.0, dt=0.01),
+}
+
+
+def make_context(G, W, n=None):
+    a = W["a"]
+    rp = rplus(a)
+    evolve = W["mode"] == "evolve"
+    n = W["n"] if n is None else n
+    cfg = G.config_default(
+        a=a, nr=W["nr"], nth=W["nth"], r_in=0.9 * rp, r_out=W["r_out"],
+        field_mode=G.FIELDS_EVOLVE if evolve else G.FIELDS_STATIC,
+        pusher=G.PUSH_HYB2, hyb_threshold=W["thr"], max_particles=n,
+        r_remove_in=rp, r_remove_out=W["r_out"], reflect=1,
+        r_abs=W.get("r_abs", 0.0), chi0=1e4 if evolve else 0.0, lambda_abs=5.0,
+        guess=G.GUESS_RK4)
+    cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
+    ctx = G.Context(cfg)
+    ctx.set_fields_wald(1.0)
+    if evolve:
+        # weight: plasma frequency omega_p dt = 0.05 at the mean density
+        # (4 pi n q^2/m = omega_p^2, n = N w / V, V ~ proper shell volume)
+        r0, r1 = rp, W["r_abs"]
+        vol = 4.0 * np.pi / 3.0 * (r1 ** 3 - r0 ** 3)
+        w = (0.05 / cfg.dt) ** 2 * vol / (4.0 * np.pi * n)
+        ctx.init_particles(G.INIT_SHELL_MJ, n, SEED + 3, r0, r1, cfg.theta0,
+                           np.pi - cfg.theta0, W["theta"], w=w)
+    else:
+        ctx.init_particles(G.INIT_SHELL_ISO, n, SEED + 2, 2.0, 30.0, cfg.theta0,
+                           np.pi - cfg.theta0, W["theta"])
+    return ctx, cfg
+
+
+def herr_percentiles(hist):
+    c = np.cumsum(hist)
+    if c[-1] == 0:
+        return {}
+    out = {}
+    for q in (50, 90, 99):
+        b = int(np.searchsorted(c, q / 100.0 * c[-1]))
+        out[f"p{q}"] = float(10 ** ((b + 1) / 2.0 - 30.0))  # upper bin edge
+    return out
+
+
+def cpu_baseline(W, cfg, sample_particles, sample_steps):
+    """The oracle on the host cores: the particle part (push + deposit) on a
+    particle sample and the grid part of a step, combined for the full
+    workload's particle count."""
+    import oracle as O
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    g = O.Grid(cfg.a, cfg.nr, cfg.nth, cfg.r_in, cfg.r_out, cfg.theta0)
+    D, B = O.wald_grid(g, 1.0)
+    G6 = [g.densitize(c, D[c]) for c in range(3)] + [g.densitize(3 + c, B[c]) for c in range(3)]
+    evolve = W["mode"] == "evolve"
+    if evolve:
+        p = O.init_particles(O.INIT_SHELL_MJ, cfg.a, SEED + 3, sample_particles,
+                             rplus(cfg.a), W["r_abs"], cfg.theta0, np.pi - cfg.theta0,
+                             W["theta"], w=1e-6)
+    else:
+        p = O.init_particles(O.INIT_SHELL_ISO, cfg.a, SEED + 2, sample_particles, 2.0, 30.0,
+                             cfg.theta0, np.pi - cfg.theta0, W["theta"])
+    P = O.push_params(cfg.a, cfg.dt, pusher=O.HYB2, guess=O.GUESS_RK4, thr=cfg.hyb_threshold,
+                      tol=cfg.tol, kmax=cfg.kmax, field_kind=O.FIELDS_GRID,
+                      r_min=cfg.r_remove_in, r_max=cfg.r_remove_out, th_lo=cfg.theta0,
+                      th_hi=np.pi - cfg.theta0)
+    t0 = time.perf_counter()
+    for _ in range(sample_steps):
+        old = p.state()[:, :3].copy()
+        alive0 = (p.flags & 1) != 0
+        O.push(P, p, grid=g, G=G6)
+        if evolve:
+            alive = alive0 & ((p.flags & 1) != 0)
+            O.deposit(g, cfg.dt, old, p.state()[:, :3], p.qm * p.w, alive.astype(np.int32))
+    t_part = (time.perf_counter() - t0) / (sample_steps * sample_particles)
+    t_grid = 0.0
+    if evolve:
+        F = O.Fields.uniform_levels(g, D, B)
+        t1 = time.perf_counter()
+        O.pic_step(P, g, F, None, absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
+        t_grid = time.perf_counter() - t1
+    n_full = W["n"]
+    rate = n_full / (t_grid + n_full * t_part)
+    return {"value": rate, "unit": "particle-steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": (f"{sample_particles} particles x {sample_steps} steps of push"
+                       + (" + deposit, plus one full grid step (Maxwell sub-steps) on the "
+                          f"{cfg.nr}x{cfg.nth} grid; rate = N / (t_grid + N t_particle) for "
+                          f"N = {n_full}" if evolve else f"; rate for N = {n_full}")),
+            "t_particle_s": t_part, "t_grid_s": t_grid}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--particles", type=int, default=0, help="override particle count")
+    ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path "
+              "is built and measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2602_07452_amd as G
+    W = dict(WORKLOADS[args.workload])
+    if args.particles:
+        W["n"] = args.particles
+    ctx, cfg = make_context(G, W)
+    print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,
+          flush=True)
+    ctx.use_graph(bool(args.graph))
+    ctx.step(args.warmup)
+    ctx.sync()
+    n_alive = ctx.diagnostics()["alive"] or W["n"]
+    ctx.enable_timing(not args.graph)
+    ctx.reset_timings()
+    d0 = ctx.diagnostics()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    ctx.sync()
+    t1 = time.perf_counter()
+    d1 = ctx.diagnostics()
+    tim = ctx.timings()
+    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    value = n_alive * args.steps / (t1 - t0)
+    print(f"[bench] {ms_step:.3f} ms/step, {value:.4e} particle-steps/s", file=sys.stderr,
+          flush=True)
+
+    # dominant kernel and its roofline
+    impl = d1["implicit_steps"] - d0["implicit_steps"]
+    iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
+    evolve = W["mode"] == "evolve"
+    flops = {
+        "push": args.steps * n_alive * (FLOP_RK4 + FLOP_SWITCH) +
+        (args.steps * n_alive - impl) * (FLOP_WEIGHTS if evolve else 0),
+        "implicit": iters * FLOP_IMR_ITER + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
+    }
+    roof = None
+    if not args.graph:
+        ms = {k: v[0] for k, v in tim.items()}
+        dom = max(ms, key=ms.get)
+        cnt = max(tim[dom][1], 1)
+        avg_s = ms[dom] / cnt * 1e-3
+        if dom in ("push", "implicit"):
+            achieved = flops[dom] / cnt / avg_s / 1e12
+            roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
+                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                    "avg_launch_ms": avg_s * 1e3}
+        else:
+            nbytes = BYTES_DEPOSIT * n_alive if dom == "deposit" else 0
+            achieved = nbytes / avg_s / 1e9
+            roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                    "avg_launch_ms": avg_s * 1e3}
+        roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
+                                      if v[1] > 0}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(W, cfg, args.cpu_sample, args.cpu_steps)
+
+    out = {
+        "metric": "particle-steps/s (gather+push+deposit) at fixed H error; learned vs plain guess",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": W["desc"], "particles": W["n"], "grid": [W["nr"], W["nth"]],
+                   "dt": cfg.dt, "pusher": "Hyb2 (RK4 -> IMR)", "threshold": cfg.hyb_threshold,
+                   "guess": "RK4 result", "fields": "FP32", "particle_state": "FP64",
+                   "graph": bool(args.graph)},
+        "implicit_fraction": impl / max(args.steps * n_alive, 1),
+        "mean_implicit_iterations": float(iters / max(impl, 1)),
+        "h_error": herr_percentiles(d1["herr_hist"]),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

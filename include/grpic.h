@@ -1,0 +1,258 @@
+/*
+ * grpic.h -- C ABI of the MI355X GRPIC particle hot path.
+ *
+ * Method: C. Meringolo & L. Rezzolla, "FPIC: a new Particle-In-Cell code for
+ * stationary and axisymmetric black-hole spacetimes", arXiv:2602.07452.
+ * The library advances charged or neutral test particles and (optionally)
+ * the electromagnetic field of a Kerr black hole (mass M = 1, spin a) in
+ * spherical Kerr-Schild coordinates (r, theta) with axisymmetric fields:
+ * field gather, particle push (RK4, implicit midpoint, Hamiltonian
+ * discrete-gradient scheme, and the Hyb1/Hyb2 hybrid switch), charge and
+ * current deposit, and the two-chain leapfrog Maxwell update (Sec. 2).
+ *
+ * Conventions
+ *  - Every entry point returns 0 on success or a negative GRPIC_E_* code;
+ *    grpic_last_error() gives a message.  No entry point aborts.
+ *  - The context owns all device memory (allocated in grpic_create and
+ *    grpic_*_particles); host buffers belong to the caller and are copied
+ *    synchronously on the context's stream unless stated otherwise.
+ *  - Particle state z = (r, theta, phi, u_r, u_theta, u_phi): contravariant
+ *    position and covariant four-velocity per unit mass (Sec. 2.2), FP64.
+ *    qm is the charge-to-mass ratio q/m in {+1, -1, 0}; w the macro weight.
+ *  - Grid (Sec. 2.1, Fig. 1): N_r x N_theta cells, r_i = r_in exp(i dlnr),
+ *    dlnr = ln(r_out / r_in) / N_r, half radii r_{i+1/2} = sqrt(r_i r_{i+1});
+ *    theta_j = theta0 + j dth, dth = (pi - 2 theta0) / N_theta.
+ *  - Field arrays exchanged through the ABI are FP32, "densitized"
+ *    (sqrt(gamma) * F at the component's Yee point), r-fastest, with shapes
+ *      D^r, J^r, B^theta : N_r     x (N_theta+1)   at (i+1/2, j)
+ *      D^th, J^th, B^r   : (N_r+1) x N_theta       at (i, j+1/2)
+ *      D^phi, J^phi, rho : (N_r+1) x (N_theta+1)   at (i, j)
+ *      B^phi             : N_r     x N_theta       at (i+1/2, j+1/2)
+ *    (row = theta index, column = r index).
+ */
+#ifndef GRPIC_H
+#define GRPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define GRPIC_OK 0
+#define GRPIC_E_INVALID (-1)   /* bad argument or configuration          */
+#define GRPIC_E_CFL (-2)       /* dt above the Courant limit of the grid */
+#define GRPIC_E_OOM (-3)       /* device allocation failed               */
+#define GRPIC_E_HIP (-4)       /* HIP runtime error                      */
+#define GRPIC_E_STATE (-5)     /* call not valid in the current state    */
+#define GRPIC_E_NODEVICE (-6)  /* no usable GPU                          */
+
+/* ---- enumerations ------------------------------------------------------*/
+enum grpic_pusher {
+  GRPIC_PUSH_RK4 = 0,  /* explicit RK4, Sec. 2.2.1                         */
+  GRPIC_PUSH_IMR = 1,  /* implicit midpoint rule, Sec. 2.2.2                */
+  GRPIC_PUSH_HAM = 2,  /* discrete-gradient scheme (neutral), Sec. 2.2.3;
+                          charged particles fall back to the IMR             */
+  GRPIC_PUSH_HYB1 = 3, /* RK4, redone implicitly when the relative growth
+                          rate of the energy violation exceeds the threshold
+                          (Sec. 3.1.2, "Hyb1")                               */
+  GRPIC_PUSH_HYB2 = 4  /* RK4, redone implicitly when the energy violation
+                          itself exceeds the threshold ("Hyb2")              */
+};
+enum grpic_guess {
+  GRPIC_GUESS_PLAIN = 0, /* implicit iteration starts from z^n             */
+  GRPIC_GUESS_RK4 = 1,   /* hybrid: starts from the rejected RK4 result    */
+  GRPIC_GUESS_MLP = 2    /* starts from the learned guess network          */
+};
+enum grpic_field_mode {
+  GRPIC_FIELDS_NONE = 0,   /* geodesic motion, no grid                     */
+  GRPIC_FIELDS_STATIC = 1, /* gather + push in fixed grid fields           */
+  GRPIC_FIELDS_EVOLVE = 2  /* full PIC step: Maxwell + gather + push +
+                              deposit                                      */
+};
+/* field time levels (Sec. 2.1 sub-steps; the push reads DH1 and BH) */
+enum grpic_level {
+  GRPIC_LEVEL_DN = 0,  /* D^{n+1}                                          */
+  GRPIC_LEVEL_DH0 = 1, /* D^{n+1/2}                                        */
+  GRPIC_LEVEL_DH1 = 2, /* D^{n+3/2}                                        */
+  GRPIC_LEVEL_BM = 3,  /* B^{n}                                            */
+  GRPIC_LEVEL_BN = 4,  /* B^{n+1}                                          */
+  GRPIC_LEVEL_BH = 5,  /* B^{n+3/2} (rebuilt every step)                   */
+  GRPIC_LEVEL_J = 6,   /* J^{n+3/2} comps 0..2, rho^{n+2} comp 3 (after a
+                          step: the current step's deposit)                */
+  GRPIC_LEVEL_JPREV = 7 /* J^{n+1/2}, rho^{n+1}                            */
+};
+/* particle flags */
+#define GRPIC_FLAG_ALIVE 1
+#define GRPIC_FLAG_IMPLICIT 2  /* last step taken by the implicit scheme   */
+#define GRPIC_FLAG_NOCONV 4    /* implicit iteration hit kmax              */
+#define GRPIC_FLAG_REMOVED 8   /* left the domain in the last step         */
+#define GRPIC_FLAG_REFLECTED 16 /* reflected at a theta edge last step     */
+
+/* ---- configuration ---------------------------------------------------- */
+typedef struct grpic_config {
+  double a;              /* spin a_* in [0, 1)                              */
+  int nr, nth;           /* grid cells (ignored for GRPIC_FIELDS_NONE)      */
+  double r_in, r_out;    /* radial extent of the grid                       */
+  double theta0;         /* theta edges at theta0, pi - theta0 (Sec. 2.5)   */
+  double dt;             /* time step                                       */
+  int field_mode;        /* enum grpic_field_mode                           */
+  int pusher;            /* enum grpic_pusher                               */
+  int guess;             /* enum grpic_guess                                */
+  double hyb_threshold;  /* Hyb1: rate bound; Hyb2: value bound             */
+  double tol;            /* implicit stopping tolerance (max relative change
+                            per component, relative to max(|z|,1))          */
+  int kmax;              /* implicit iteration cap (<= 255)                 */
+  double ham_eps;        /* |dx| below which the DG scheme uses analytic
+                            derivatives (App. D: 1e-10)                    */
+  double r_abs, chi0, lambda_abs; /* absorbing layer, eqs. abs0-abs2;
+                                     chi0 = 0 disables                      */
+  double r_remove_in, r_remove_out; /* particles outside are removed        */
+  int reflect;           /* reflect particles at the theta edges (1) or not */
+  long max_particles;    /* capacity                                        */
+  int sort_every;        /* re-sort particles by tile every N steps (0: only
+                            when particles are loaded)                      */
+  int tile_r, tile_th;   /* tile size in cells for sorting / deposit bins  */
+  int block;             /* threads per block for particle kernels (0 = 256)*/
+  int persistent_waves;  /* waves per CU of the implicit-queue kernel (0=8) */
+} grpic_config;
+
+/* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */
+int grpic_config_default(grpic_config *cfg);
+
+typedef struct grpic_ctx grpic_ctx;
+
+/* Validate cfg, allocate grid/field storage on the current HIP device and
+ * tabulate the metric at every Yee point (Sec. 2.1, "computed only
+ * initially").  Errors: GRPIC_E_INVALID (ranges), GRPIC_E_CFL (dt above the
+ * grid's Courant limit for field_mode EVOLVE), GRPIC_E_OOM, GRPIC_E_HIP,
+ * GRPIC_E_NODEVICE.  *out is NULL on failure.                             */
+int grpic_create(const grpic_config *cfg, grpic_ctx **out);
+void grpic_destroy(grpic_ctx *ctx);
+/* Message of the last failing call on ctx (ctx may be NULL: last failure
+ * of grpic_create).  Owned by the library.                                */
+const char *grpic_last_error(const grpic_ctx *ctx);
+/* Largest stable dt of the field solver on this grid (Courant limit).    */
+int grpic_cfl_dt(const grpic_config *cfg, double *dt_out);
+
+/* Run all following work on the given hipStream_t (NULL: the context's own
+ * stream).  The caller keeps ownership of the stream.                     */
+int grpic_set_stream(grpic_ctx *ctx, void *hip_stream);
+int grpic_sync(grpic_ctx *ctx);
+
+/* Host copies of the grid coordinates: rn[N_r+1], rh[N_r], tn[N_th+1],
+ * th[N_th].  Any pointer may be NULL.                                     */
+int grpic_grid_coords(grpic_ctx *ctx, double *rn, double *rh, double *tn,
+                      double *th);
+
+/* ---- fields ----------------------------------------------------------- */
+/* Wald vacuum field of strength B0 on every D and B level (App. B.1, with
+ * E_i = +d_i A_0 and D_i from eq. Ei); J and rho are cleared.             */
+int grpic_set_fields_wald(grpic_ctx *ctx, double B0);
+/* Split monopole (App. B.2): flux function 4 B0 zeta(theta)(1 - cos theta),
+ * zeta = (2/pi) atan(zeta0 (theta - pi/2)); D = 0.                        */
+int grpic_set_fields_split_monopole(grpic_ctx *ctx, double B0, double zeta0);
+/* Copy one densitized component (comp 0..2 = D^r,D^th,D^ph for D levels,
+ * B^r,B^th,B^ph for B levels; J levels: 0..2 = J^r,J^th,J^ph, 3 = rho)
+ * from / to a host FP32 array of the component's shape.                   */
+int grpic_set_field(grpic_ctx *ctx, int level, int comp, const float *host);
+int grpic_get_field(grpic_ctx *ctx, int level, int comp, float *host);
+
+/* ---- particles -------------------------------------------------------- */
+enum grpic_init_kind {
+  GRPIC_INIT_ORBITS = 0,    /* Schwarzschild (a = 0) test orbits: r ~
+                               U[r0,r1], theta ~ U[t0,t1], circular orbit
+                               constants, even ids circular, odd ids with a
+                               u_r offset ~ U[-p0, p0]; neutral             */
+  GRPIC_INIT_SHELL_ISO = 1, /* uniform in proper volume over the shell,
+                               isotropic FIDO momenta |u| ~ U[0, p0];
+                               q/m = +1 (even ids), -1 (odd ids)            */
+  GRPIC_INIT_SHELL_MJ = 2   /* e+/e- pairs sharing a position uniform in
+                               proper volume, Maxwell-Juettner FIDO momenta
+                               at temperature p0                            */
+};
+typedef struct grpic_init_spec {
+  int kind;              /* enum grpic_init_kind                            */
+  long n;                /* number of particles (<= max_particles)          */
+  uint64_t seed;         /* SplitMix64 seed (counter-based, per particle)   */
+  double r0, r1, t0, t1; /* sampling shell                                  */
+  double p0;             /* momentum scale / temperature / u_r spread       */
+  double w;              /* macro weight of every particle                  */
+} grpic_init_spec;
+/* Sample the initial particles on the device, compute H_0, sort them by
+ * tile and deposit rho at the initial positions (for EVOLVE).            */
+int grpic_init_particles(grpic_ctx *ctx, const grpic_init_spec *spec);
+/* Load n particles from host arrays (ids 0..n-1 in array order).  H0 and
+ * herr may be NULL (H0 = e(z^0) = alpha Gamma - beta^r u_r, herr = 0).    */
+int grpic_load_particles(grpic_ctx *ctx, long n, const double *r,
+                         const double *th, const double *ph, const double *ur,
+                         const double *uth, const double *uph,
+                         const double *qm, const double *w, const double *H0,
+                         const double *herr);
+/* Copy the particles back in id order.  Any pointer may be NULL.  flags
+ * and iters describe the last step.                                       */
+int grpic_get_particles(grpic_ctx *ctx, long n, double *r, double *th,
+                        double *ph, double *ur, double *uth, double *uph,
+                        double *qm, double *w, double *H0, double *herr,
+                        int32_t *flags, int32_t *iters);
+int grpic_num_particles(grpic_ctx *ctx, long *n);
+
+/* ---- stepping ---------------------------------------------------------- */
+/* Advance nsteps steps, asynchronously on the context's stream.           */
+int grpic_step(grpic_ctx *ctx, int nsteps);
+/* Capture one step in a hipGraph and replay it for grpic_step (1) or go
+ * back to eager launches (0).                                             */
+int grpic_use_graph(grpic_ctx *ctx, int enable);
+
+/* ---- diagnostics ------------------------------------------------------- */
+#define GRPIC_HIST_BINS 64
+typedef struct grpic_diag {
+  long steps;            /* steps taken since load                          */
+  long alive;            /* particles alive                                 */
+  long removed;          /* removed since load                              */
+  long implicit_steps;   /* particle-steps taken implicitly (cumulative)    */
+  long noconv;           /* implicit solves that hit kmax (cumulative)      */
+  long reflected;        /* pole reflections (cumulative)                   */
+  long iter_hist[GRPIC_HIST_BINS]; /* implicit iteration counts             */
+  long herr_hist[GRPIC_HIST_BINS]; /* log10 energy-violation bins of the
+                                      last step: bin b holds values in
+                                      [10^(b/2-30), 10^((b+1)/2-30))       */
+} grpic_diag;
+int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
+/* Grid diagnostics on the integer chain: max |Gauss residual| over interior
+ * nodes (eq. m1, densitized), max |div B| (eq. m2) and the Poynting
+ * luminosity P(r_i) of eq. Pbz at every node radius (pbz may be NULL).    */
+int grpic_field_diagnostics(grpic_ctx *ctx, double *gauss_max,
+                            double *divb_max, double *pbz);
+
+/* ---- timing ----------------------------------------------------------- */
+enum grpic_kernel_id {
+  GRPIC_K_FIELDS = 0,   /* Maxwell sub-steps 1-4 and 7-10                  */
+  GRPIC_K_PUSH = 1,     /* explicit pass: gather + RK4 + switch            */
+  GRPIC_K_IMPLICIT = 2, /* implicit-queue pass                             */
+  GRPIC_K_DEPOSIT = 3,  /* deposit + finalize                              */
+  GRPIC_K_SORT = 4,     /* tile sort                                       */
+  GRPIC_K_GUESS = 5,    /* learned guess                                   */
+  GRPIC_K_COUNT = 6
+};
+/* Enable (1) or disable (0) HIP-event timing of each kernel group on the
+ * context's stream; grpic_get_timings returns the summed milliseconds and
+ * the number of timed launches per group since the last reset.            */
+int grpic_enable_timing(grpic_ctx *ctx, int enable);
+int grpic_get_timings(grpic_ctx *ctx, double *ms, long *count);
+int grpic_reset_timings(grpic_ctx *ctx);
+
+/* ---- learned implicit guess (project extension, not in the paper) ----- */
+#define GRPIC_MLP_NPARAM 5510 /* 14 -> 64 -> 64 -> 6, GELU                */
+/* Parameters packed W1[64][14] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]
+ * (FP32; the device keeps BF16 copies of the weights), plus feature
+ * normalisation mean[14], inv_std[14] and output scale[6].               */
+int grpic_mlp_set(grpic_ctx *ctx, const float *theta, const float *mean,
+                  const float *inv_std, const float *scale);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

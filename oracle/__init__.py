@@ -108,6 +108,13 @@ def metric_deriv(a, r, th):
     return out
 
 
+def metric_divdiff(a, k, r0, t0, r1, t1):
+    q = np.zeros(6)
+    lib().om_metric_divdiff(C.c_double(a), k, C.c_double(r0), C.c_double(t0),
+                            C.c_double(r1), C.c_double(t1), _p(q))
+    return q
+
+
 def energy(a, z):
     z = _f64(z)
     return lib().om_energy(C.c_double(a), _p(z))

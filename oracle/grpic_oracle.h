@@ -38,6 +38,11 @@ extern "C" {
 void om_metric(double a, double r, double th, double *out);
 /* out[12] = d_r,d_th of alpha, beta^r, gi_rr, gi_thth, gi_phph, gi_rph      */
 void om_metric_deriv(double a, double r, double th, double *out);
+/* q[6] = divided differences [f(x1) - f(x0)] / (x1^k - x0^k), f = alpha,
+ * beta^r, gamma^rr, gamma^thth, gamma^phph, gamma^rph; x0, x1 differ only in
+ * coordinate k (0 = r, 1 = theta); evaluated without cancellation           */
+void om_metric_divdiff(double a, int k, double r0, double t0, double r1,
+                       double t1, double *q);
 /* e = alpha Gamma - beta^r u_r  (eq. Ham with A_0 dropped)                  */
 double om_energy(double a, const double *z);
 /* equations of motion (eqs. p1, p2, O1, O2) at fields D^i, B^i             */

@@ -273,9 +273,11 @@ int om_step_imr(const om_push_params *P, const om_grid *g,
  * orders r->theta->phi with x before u, and their time reverses).  Each
  * ordering telescopes, so H is conserved exactly up to round-off.
  * The u-quotients are rationalised exactly; the x-quotients use the exact
- * product split d(alpha Gamma) = <alpha> dGamma + <Gamma> dalpha; a metric
- * quotient df/dx is replaced by the analytic derivative at the midpoint
- * when |dx| < eps (App. D, last paragraph).
+ * product split d(alpha Gamma) = <alpha> dGamma + <Gamma> dalpha with the
+ * metric quotients df/dx evaluated as cancellation-free divided differences
+ * (same value as the plain quotient in exact arithmetic); a quotient is
+ * replaced by the analytic derivative at the midpoint when |dx| < eps
+ * (App. D, last paragraph).
  * Variables: 0 r, 1 theta, 2 phi, 3 u_r, 4 u_theta, 5 u_phi.
  * ------------------------------------------------------------------------ */
 static const int om_orders[6][6] = {
@@ -286,6 +288,52 @@ static double gamma_of(const double *m, const double *y) {
   double ur = y[3], ut = y[4], up = y[5];
   return sqrt(1.0 + m[6] * ur * ur + m[7] * ut * ut + m[8] * up * up +
               2.0 * m[9] * ur * up);
+}
+
+/* Divided differences [f(x') - f(x)] / (x'^k - x^k) of the metric
+ * functions alpha, beta^r, gamma^rr, gamma^thth, gamma^phph, gamma^rph between
+ * two positions that differ only in coordinate k (0 = r, 1 = theta),
+ * written without cancellation (identical to the plain quotient in exact
+ * arithmetic, but accurate to rounding for any step):
+ *   r:     d(rho^2) = r + r',        d(S) = r + r' + 2   (S = rho^2 + 2r)
+ *   theta: d(cos^2) = -sin(t + t') sin(t' - t)/(t' - t) = -d(sin^2)
+ * and d(1/g) = -d(g)/(g g'), d(g h) = g' d(h) + h d(g),
+ * d(sqrt g) = d(g)/(sqrt g + sqrt g').                                      */
+static double sinc(double x) {
+  return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x;
+}
+
+void om_metric_divdiff(double a, int k, double r0, double t0, double r1,
+                       double t1, double *q) {
+  double A = a * a;
+  double c0 = cos(t0), c1 = cos(t1), s0 = sin(t0), s1 = sin(t1);
+  double C0 = c0 * c0, C1 = c1 * c1, Ss0 = s0 * s0, Ss1 = s1 * s1;
+  double P0 = r0 * r0 + A * C0, P1 = r1 * r1 + A * C1; /* rho^2 */
+  double S0 = P0 + 2.0 * r0, S1 = P1 + 2.0 * r1;
+  double dP, dS, dSs, dC;
+  if (k == 0) {
+    dP = r0 + r1;
+    dS = r0 + r1 + 2.0;
+    dSs = 0.0;
+    dC = 0.0;
+  } else {
+    dC = -sin(t0 + t1) * sinc(t1 - t0);
+    dSs = -dC;
+    dP = A * dC;
+    dS = A * dC;
+  }
+  double d_irho2 = -dP / (P0 * P1);
+  /* 1/xi = rho^2 / S */
+  double d_ixi = (dP * S0 - P0 * dS) / (S0 * S1);
+  double ixi0 = P0 / S0, ixi1 = P1 / S1;
+  double al0 = sqrt(ixi0), al1 = sqrt(ixi1);
+  q[0] = d_ixi / (al0 + al1);               /* alpha = sqrt(1/xi)        */
+  q[1] = -d_ixi;                            /* beta^r = 1 - 1/xi         */
+  q[2] = A * (Ss1 * d_irho2 + dSs / P0) + d_ixi; /* gamma^rr             */
+  q[3] = d_irho2;                           /* gamma^thth                */
+  double dPS = P1 * dSs + Ss0 * dP;         /* d(rho^2 sin^2)            */
+  q[4] = -dPS / (P0 * Ss0 * P1 * Ss1);      /* gamma^phph                */
+  q[5] = a * d_irho2;                       /* gamma^rph                 */
 }
 
 /* [H(y1) - H(y0)] / (y1[k] - y0[k]) for y0, y1 differing only in slot k   */
@@ -314,9 +362,11 @@ static double ham_quotient(double a, double eps, int k, const double *y0,
   double dx = y1[k] - y0[k];
   double qa, qb, qg[4];
   if (fabs(dx) >= eps) {
-    qa = (m1[0] - m0[0]) / dx;
-    qb = (m1[1] - m0[1]) / dx;
-    for (int i = 0; i < 4; ++i) qg[i] = (m1[6 + i] - m0[6 + i]) / dx;
+    double q[6];
+    om_metric_divdiff(a, k, y0[0], y0[1], y1[0], y1[1], q);
+    qa = q[0];
+    qb = q[1];
+    for (int i = 0; i < 4; ++i) qg[i] = q[2 + i];
   } else {
     double d[12];
     double rm = (k == 0) ? 0.5 * (y0[0] + y1[0]) : y0[0];

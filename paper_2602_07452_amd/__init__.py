@@ -1,0 +1,263 @@
+"""Python binding of the MI355X GRPIC library (``libgrpic.so``, include/grpic.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  The binding refuses to work without the built library (there
+is no CPU fallback).  Names follow the C ABI without the ``grpic_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrpic.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "grpic.h")
+_LIB = None
+
+# enums (include/grpic.h)
+PUSH_RK4, PUSH_IMR, PUSH_HAM, PUSH_HYB1, PUSH_HYB2 = 0, 1, 2, 3, 4
+GUESS_PLAIN, GUESS_RK4, GUESS_MLP = 0, 1, 2
+FIELDS_NONE, FIELDS_STATIC, FIELDS_EVOLVE = 0, 1, 2
+LEVEL_DN, LEVEL_DH0, LEVEL_DH1, LEVEL_BM, LEVEL_BN, LEVEL_BH, LEVEL_J, LEVEL_JPREV = range(8)
+INIT_ORBITS, INIT_SHELL_ISO, INIT_SHELL_MJ = 0, 1, 2
+FLAG_ALIVE, FLAG_IMPLICIT, FLAG_NOCONV, FLAG_REMOVED, FLAG_REFLECTED = 1, 2, 4, 8, 16
+K_FIELDS, K_PUSH, K_IMPLICIT, K_DEPOSIT, K_SORT, K_GUESS = range(6)
+KERNEL_NAMES = ("fields", "push", "implicit", "deposit", "sort", "guess")
+HIST_BINS = 64
+MLP_NPARAM = 5510
+
+
+class GrpicError(RuntimeError):
+    pass
+
+
+class Config(C.Structure):
+    _fields_ = [("a", C.c_double), ("nr", C.c_int), ("nth", C.c_int),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("theta0", C.c_double),
+                ("dt", C.c_double), ("field_mode", C.c_int), ("pusher", C.c_int),
+                ("guess", C.c_int), ("hyb_threshold", C.c_double), ("tol", C.c_double),
+                ("kmax", C.c_int), ("ham_eps", C.c_double), ("r_abs", C.c_double),
+                ("chi0", C.c_double), ("lambda_abs", C.c_double),
+                ("r_remove_in", C.c_double), ("r_remove_out", C.c_double),
+                ("reflect", C.c_int), ("max_particles", C.c_long),
+                ("sort_every", C.c_int), ("tile_r", C.c_int), ("tile_th", C.c_int),
+                ("block", C.c_int), ("persistent_waves", C.c_int)]
+
+
+class InitSpec(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_long), ("seed", C.c_uint64),
+                ("r0", C.c_double), ("r1", C.c_double), ("t0", C.c_double),
+                ("t1", C.c_double), ("p0", C.c_double), ("w", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("steps", C.c_long), ("alive", C.c_long), ("removed", C.c_long),
+                ("implicit_steps", C.c_long), ("noconv", C.c_long),
+                ("reflected", C.c_long), ("iter_hist", C.c_long * HIST_BINS),
+                ("herr_hist", C.c_long * HIST_BINS)]
+
+
+def lib():
+    """Load libgrpic.so (built by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise GrpicError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.grpic_last_error.restype = C.c_char_p
+        L.grpic_last_error.argtypes = [C.c_void_p]
+        L.grpic_create.argtypes = [C.POINTER(Config), C.POINTER(C.c_void_p)]
+        L.grpic_destroy.argtypes = [C.c_void_p]
+        L.grpic_destroy.restype = None
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the functions declared in include/grpic.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(grpic_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _check(rc, ctx=None):
+    if rc != 0:
+        msg = lib().grpic_last_error(ctx)
+        raise GrpicError(f"grpic error {rc}: {msg.decode() if msg else ''}")
+
+
+def config_default(**kw) -> Config:
+    cfg = Config()
+    _check(lib().grpic_config_default(C.byref(cfg)))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def cfl_dt(cfg: Config) -> float:
+    out = C.c_double()
+    _check(lib().grpic_cfl_dt(C.byref(cfg), C.byref(out)))
+    return out.value
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+class Context:
+    """One GRPIC simulation context on the current HIP device."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        h = C.c_void_p()
+        _check(lib().grpic_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().grpic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _c(self, fn, *args):
+        _check(getattr(lib(), fn)(self._h, *args), self._h)
+
+    # -- streams
+    def set_stream(self, stream_handle: int | None):
+        self._c("grpic_set_stream", C.c_void_p(stream_handle or 0))
+
+    def sync(self):
+        self._c("grpic_sync")
+
+    # -- grid
+    def grid_coords(self):
+        nr, nth = self.cfg.nr, self.cfg.nth
+        rn, rh, tn, th = np.zeros(nr + 1), np.zeros(nr), np.zeros(nth + 1), np.zeros(nth)
+        self._c("grpic_grid_coords", _dp(rn), _dp(rh), _dp(tn), _dp(th))
+        return rn, rh, tn, th
+
+    def field_shape(self, level, comp):
+        """(rows = theta, cols = r) of a densitized component."""
+        nr, nth = self.cfg.nr, self.cfg.nth
+        if LEVEL_BM <= level <= LEVEL_BH:
+            rh, thh = comp in (1, 2), comp in (0, 2)
+        else:
+            rh, thh = comp == 0, comp == 1
+        return (nth if thh else nth + 1, nr if rh else nr + 1)
+
+    def set_fields_wald(self, B0):
+        self._c("grpic_set_fields_wald", C.c_double(B0))
+
+    def set_fields_split_monopole(self, B0, zeta0):
+        self._c("grpic_set_fields_split_monopole", C.c_double(B0), C.c_double(zeta0))
+
+    def set_field(self, level, comp, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float32)
+        if a.shape != self.field_shape(level, comp):
+            raise ValueError(f"shape {a.shape} != {self.field_shape(level, comp)}")
+        self._c("grpic_set_field", level, comp, a.ctypes.data_as(C.POINTER(C.c_float)))
+
+    def get_field(self, level, comp):
+        a = np.zeros(self.field_shape(level, comp), dtype=np.float32)
+        self._c("grpic_get_field", level, comp, a.ctypes.data_as(C.POINTER(C.c_float)))
+        return a
+
+    # -- particles
+    def init_particles(self, kind, n, seed, r0, r1, t0, t1, p0, w=1.0):
+        spec = InitSpec(kind, n, seed, r0, r1, t0, t1, p0, w)
+        self._c("grpic_init_particles", C.byref(spec))
+
+    def load_particles(self, z, qm, w=None, H0=None, herr=None):
+        z = np.atleast_2d(_f64(z))
+        n = z.shape[0]
+        cols = [np.ascontiguousarray(z[:, i]) for i in range(6)]
+        qm = _f64(np.broadcast_to(qm, (n,)))
+        w = _f64(np.ones(n) if w is None else np.broadcast_to(w, (n,)))
+        H0a = None if H0 is None else _f64(H0)
+        herra = None if herr is None else _f64(herr)
+        H0p = _dp(H0a) if H0a is not None else None
+        hp = _dp(herra) if herra is not None else None
+        self._c("grpic_load_particles", C.c_long(n), *[_dp(c) for c in cols],
+                _dp(qm), _dp(w), H0p, hp)
+
+    def num_particles(self):
+        n = C.c_long()
+        self._c("grpic_num_particles", C.byref(n))
+        return n.value
+
+    def get_particles(self):
+        n = self.num_particles()
+        out = {k: np.zeros(n) for k in ("r", "th", "ph", "ur", "uth", "uph", "qm", "w",
+                                         "H0", "herr")}
+        flags = np.zeros(n, np.int32)
+        iters = np.zeros(n, np.int32)
+        ip = C.POINTER(C.c_int32)
+        self._c("grpic_get_particles", C.c_long(n),
+                *[_dp(out[k]) for k in ("r", "th", "ph", "ur", "uth", "uph", "qm", "w",
+                                         "H0", "herr")],
+                flags.ctypes.data_as(ip), iters.ctypes.data_as(ip))
+        out["flags"], out["iters"] = flags, iters
+        out["z"] = np.stack([out[k] for k in ("r", "th", "ph", "ur", "uth", "uph")], axis=1)
+        return out
+
+    # -- stepping
+    def step(self, nsteps=1):
+        self._c("grpic_step", C.c_int(nsteps))
+
+    def use_graph(self, enable=True):
+        self._c("grpic_use_graph", C.c_int(1 if enable else 0))
+
+    # -- diagnostics
+    def diagnostics(self):
+        d = Diag()
+        self._c("grpic_get_diagnostics", C.byref(d))
+        return {"steps": d.steps, "alive": d.alive, "removed": d.removed,
+                "implicit_steps": d.implicit_steps, "noconv": d.noconv,
+                "reflected": d.reflected, "iter_hist": np.array(d.iter_hist[:]),
+                "herr_hist": np.array(d.herr_hist[:])}
+
+    def field_diagnostics(self):
+        g, b = C.c_double(), C.c_double()
+        p = np.zeros(self.cfg.nr + 1)
+        self._c("grpic_field_diagnostics", C.byref(g), C.byref(b), _dp(p))
+        return g.value, b.value, p
+
+    # -- timing
+    def enable_timing(self, enable=True):
+        self._c("grpic_enable_timing", C.c_int(1 if enable else 0))
+
+    def reset_timings(self):
+        self._c("grpic_reset_timings")
+
+    def timings(self):
+        ms = np.zeros(6)
+        cnt = np.zeros(6, dtype=np.int64)
+        self._c("grpic_get_timings", _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_long)))
+        return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(6)}
+
+    # -- learned guess
+    def mlp_set(self, theta, mean, inv_std, scale):
+        keep = [np.ascontiguousarray(x, dtype=np.float32) for x in (theta, mean, inv_std, scale)]
+        assert keep[0].size == MLP_NPARAM and keep[1].size == 14 and keep[3].size == 6
+        self._c("grpic_mlp_set", *[k.ctypes.data_as(C.POINTER(C.c_float)) for k in keep])

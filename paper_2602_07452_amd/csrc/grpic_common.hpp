@@ -1,0 +1,174 @@
+// grpic_common.hpp -- shared declarations of the GRPIC HIP library: device
+// views of the particle and field storage, the context, and the launchers
+// implemented in each translation unit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/grpic.h"
+
+namespace grpic {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kHistBins = GRPIC_HIST_BINS;
+
+// ------------------------------------------------------------ particle views
+struct ParticleView {
+  long n;
+  double *r, *th, *ph, *ur, *uth, *uph;  // state z
+  double *H0, *herr, *w;
+  int8_t* qm;                            // q/m in {+1, -1, 0}
+  uint8_t *flags, *iters;
+  uint32_t* id;
+  double* W[4];                          // deposit weights at x (current)
+  int* cell;                             // node cell index q * nr + p
+  double* Wn[4];                         // weights at the pushed position
+  int* celln;
+  double *r_old, *th_old, *dphi;         // previous position, phi change
+};
+
+// device counters written by the particle kernels
+struct Stats {
+  unsigned long long implicit_steps, noconv, removed, reflected, alive;
+  unsigned long long iter_hist[kHistBins];
+  unsigned long long herr_hist[kHistBins];
+  unsigned int queue_count;   // implicit-queue length of the current step
+  unsigned int work_counter;  // persistent-kernel work cursor
+  unsigned int guess_counter; // learned-guess kernel work cursor
+  unsigned int pad;
+};
+
+// fixed-point charge accumulators (int64, deterministic under atomics)
+struct DepositAcc {
+  long long *Q, *P, *Fr, *Ft;  // rho (nodes), J^phi (nodes), r-flux (hn),
+                               // theta-flux (nh)
+  double scale;                // value -> integer units
+};
+
+struct Level3 {
+  float* c[3];
+};
+
+struct Level4 {
+  float* c[4];
+};
+
+struct Tables {
+  // per Yee position type t (0 hn, 1 nh, 2 nn, 3 hh) FP32 coefficients
+  // k_rr = alpha g_rr / sqrt(g), k_tt = alpha g_thth / sqrt(g),
+  // k_pp = alpha g_phph / sqrt(g), k_rp = alpha g_rph / sqrt(g), beta^r,
+  // sqrt(g)
+  float *krr[4], *ktt[4], *kpp[4], *krp[4], *beta[4], *sg[4];
+  float *damp_n, *damp_h;  // absorber factor exp(-chi dt) at r_i, r_{i+1/2}
+  float *inv_drn;          // 1/(r_{i+1} - r_i), i < nr
+  float *inv_drd;          // 1/(r_{i+1/2} - r_{i-1/2}), 0 < i < nr
+};
+
+}  // namespace grpic
+
+// ------------------------------------------------------------------ context
+struct grpic_ctx {
+  grpic_config cfg;
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  std::string err;
+  // grid
+  int nr = 0, nth = 0;
+  double dlnr = 0, dth = 0;
+  std::vector<double> h_rn, h_rh, h_tn, h_th;
+  double *rn = nullptr, *rh = nullptr, *tn = nullptr, *th = nullptr;
+  double *idrn = nullptr, *idrh = nullptr;
+  grpic::Tables tab{};
+  // field levels
+  grpic::Level3 D[3]{};  // index: 0 = Dn, 1 = Dh0, 2 = Dh1
+  grpic::Level3 B[3]{};  // 0 = Bm, 1 = Bn, 2 = Bh
+  grpic::Level3 E{}, H{};
+  float* J[2][4]{};      // [cur/prev][J^r, J^th, J^phi, rho]
+  int jcur = 0;
+  grpic::DepositAcc acc{};
+  // particles
+  long n = 0, cap = 0;
+  grpic::ParticleView pv{};
+  grpic::ParticleView alt{};  // second buffers of the sorted arrays
+  double* gz[6]{};       // implicit guesses by queue slot
+  int* queue = nullptr;
+  grpic::Stats* stats = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int* tile_count = nullptr;
+  int* tile_offset = nullptr;
+  int ntiles = 0;
+  double qw_max = 0;
+  long steps = 0;
+  // learned guess
+  bool mlp_ready = false;
+  void* mlp = nullptr;
+  // graph
+  bool use_graph = false;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_parity = -1;
+  // timing
+  bool timing = false;
+  double t_ms[GRPIC_K_COUNT]{};
+  long t_count[GRPIC_K_COUNT]{};
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+};
+
+#define GRPIC_HIP(call)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess) {                                               \
+      throw grpic::Error(GRPIC_E_HIP, std::string(#call) + ": " +         \
+                                          hipGetErrorString(e_));         \
+    }                                                                     \
+  } while (0)
+
+namespace grpic {
+
+struct Error {
+  int code;
+  std::string msg;
+  Error(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// launchers (defined in the .hip translation units)
+void launch_metric_tables(grpic_ctx* c);
+void launch_wald(grpic_ctx* c, double B0);
+void launch_split_monopole(grpic_ctx* c, double B0, double zeta0);
+void launch_fields_step_pre(grpic_ctx* c);   // sub-steps 1-4
+void launch_fields_step_post(grpic_ctx* c);  // sub-steps 7-10
+void launch_fill(grpic_ctx* c, void* p, size_t bytes);
+void launch_push(grpic_ctx* c);              // sub-step 5
+void launch_deposit(grpic_ctx* c);           // sub-step 6
+void launch_deposit_initial(grpic_ctx* c);
+void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,
+                           const double* mj_table, int mj_k, double mj_h);
+void launch_energy_H0(grpic_ctx* c);
+void launch_sort(grpic_ctx* c);
+void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
+                       double* pbz);
+void launch_guess(grpic_ctx* c);
+void mlp_upload(grpic_ctx* c, const float* theta, const float* mean,
+                const float* inv_std, const float* scale);
+void mlp_free(grpic_ctx* c);
+
+// timing helpers (api.hip)
+void time_begin(grpic_ctx* c, int kid, hipEvent_t* a);
+void time_end(grpic_ctx* c, int kid, hipEvent_t a);
+
+inline unsigned grid_for(long n, int block) {
+  long g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace grpic

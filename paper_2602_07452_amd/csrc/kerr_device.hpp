@@ -1,0 +1,287 @@
+// kerr_device.hpp -- FP64 device math of the GRPIC pusher: Kerr-Schild 3+1
+// metric and its analytic derivatives (App. A; Sec. 2.2), the particle
+// equations of motion (eqs. p1, p2, O1, O2) and the metric-weighted gather
+// of the staggered grid fields.
+//
+// Forms used here (M = 1): with S = rho^2 + 2r = rho^2 xi,
+//   1/xi = rho^2/S, alpha = sqrt(rho^2/S), beta^r = 2r/S,
+//   sqrt(gamma) = |sin theta| sqrt(rho^2 S),
+// which avoid most divisions; gamma_{r phi} = -a xi sin^2 theta (the value
+// that inverts the printed gamma^{ij}).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grpic_common.hpp"
+
+namespace grpic {
+
+struct Met {
+  double s, c;                 // sin, cos theta
+  double alpha, betar;         // lapse, radial shift
+  double grr, gtt, gpp, grp;   // gamma_ij
+  double irr, itt, ipp, irp;   // gamma^ij
+  double sg;                   // sqrt(gamma)
+};
+
+struct DMet {  // [0] = d/dr, [1] = d/dtheta
+  double da[2], db[2], drr[2], dtt[2], dpp[2], drp[2];
+};
+
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
+  double s, c;
+  sincos(th, &s, &c);
+  double a2 = a * a, s2 = s * s;
+  double rho2 = r * r + a2 * c * c;
+  double S = rho2 + 2.0 * r;
+  double irho2 = rcp(rho2), iS = rcp(S);
+  double ixi = rho2 * iS, xi = S * irho2;
+  m.s = s;
+  m.c = c;
+  m.alpha = sqrt(ixi);
+  m.betar = 2.0 * r * iS;
+  m.grr = xi;
+  m.gtt = rho2;
+  m.grp = -a * xi * s2;
+  m.gpp = s2 * (rho2 + a2 * xi * s2);
+  m.irr = a2 * s2 * irho2 + ixi;
+  m.itt = irho2;
+  m.irp = a * irho2;
+  m.ipp = irho2 * rcp(s2);
+  m.sg = fabs(s) * sqrt(rho2 * S);
+}
+
+// metric plus derivatives of alpha, beta^r and gamma^ij
+__device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
+                                         DMet& d) {
+  double s, c;
+  sincos(th, &s, &c);
+  double a2 = a * a, s2 = s * s, sc = s * c;
+  double rho2 = r * r + a2 * c * c;
+  double S = rho2 + 2.0 * r;
+  double irho2 = rcp(rho2), iS = rcp(S), is2 = rcp(s2);
+  double ixi = rho2 * iS, xi = S * irho2;
+  double alpha = sqrt(ixi);
+  m.s = s;
+  m.c = c;
+  m.alpha = alpha;
+  m.betar = 2.0 * r * iS;
+  m.grr = xi;
+  m.gtt = rho2;
+  m.grp = -a * xi * s2;
+  m.gpp = s2 * (rho2 + a2 * xi * s2);
+  m.irr = a2 * s2 * irho2 + ixi;
+  m.itt = irho2;
+  m.irp = a * irho2;
+  m.ipp = irho2 * is2;
+  m.sg = fabs(s) * sqrt(rho2 * S);
+  double i4 = irho2 * irho2, ixi2 = ixi * ixi;
+  double dr2[2] = {2.0 * r, -2.0 * a2 * sc};
+  double dxi[2] = {2.0 * irho2 * (1.0 - 2.0 * r * r * irho2),
+                   4.0 * r * a2 * sc * i4};
+  double ds2[2] = {0.0, 2.0 * sc};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    d.da[k] = -0.5 * dxi[k] * alpha * ixi;
+    d.db[k] = dxi[k] * ixi2;
+    d.drr[k] = a2 * (ds2[k] * irho2 - s2 * dr2[k] * i4) - dxi[k] * ixi2;
+    d.dtt[k] = -dr2[k] * i4;
+    d.dpp[k] = -(dr2[k] * s2 + rho2 * ds2[k]) * (i4 * is2 * is2);
+    d.drp[k] = -a * dr2[k] * i4;
+  }
+}
+
+// Divided differences [f(x1) - f(x0)] / (x1^k - x0^k) of f = alpha, beta^r,
+// gamma^rr, gamma^thth, gamma^phph, gamma^rph for positions that differ in
+// coordinate k only (0 = r, 1 = theta), free of cancellation: with
+// P = rho^2 and S = rho^2 + 2r,
+//   k = r:     dP = r0 + r1, dS = dP + 2;
+//   k = theta: d(cos^2) = -sin(t0 + t1) sin(t1 - t0) / (t1 - t0) = -d(sin^2),
+//              dP = dS = a^2 d(cos^2);
+// then d(1/g) = -dg / (g0 g1), d(g h) = g1 dh + h0 dg, d(sqrt g) = dg /
+// (sqrt g0 + sqrt g1).  m0, m1 are the metrics at x0, x1.
+__device__ __forceinline__ void metric_dd(double a, int k, double r0,
+                                          double r1, double dx, const Met& m0,
+                                          const Met& m1, double* q) {
+  const double A = a * a;
+  double C0 = m0.c * m0.c, C1 = m1.c * m1.c;
+  double Ss0 = m0.s * m0.s, Ss1 = m1.s * m1.s;
+  double P0 = r0 * r0 + A * C0, P1 = r1 * r1 + A * C1;
+  double S0 = P0 + 2.0 * r0, S1 = P1 + 2.0 * r1;
+  double dP, dS, dSs;
+  if (k == 0) {
+    dP = r0 + r1;
+    dS = dP + 2.0;
+    dSs = 0.0;
+  } else {
+    double sinc = fabs(dx) < 1e-4 ? 1.0 - dx * dx * (1.0 / 6.0) : sin(dx) / dx;
+    double s01 = m0.s * m1.c + m0.c * m1.s;  // sin(t0 + t1)
+    double dC = -s01 * sinc;
+    dSs = -dC;
+    dP = A * dC;
+    dS = dP;
+  }
+  double iP01 = 1.0 / (P0 * P1);
+  double d_irho2 = -dP * iP01;
+  double d_ixi = (dP * S0 - P0 * dS) / (S0 * S1);
+  q[0] = d_ixi / (m0.alpha + m1.alpha);
+  q[1] = -d_ixi;
+  q[2] = A * (Ss1 * d_irho2 + dSs / P0) + d_ixi;
+  q[3] = d_irho2;
+  q[4] = -(P1 * dSs + Ss0 * dP) * iP01 / (Ss0 * Ss1);
+  q[5] = a * d_irho2;
+}
+
+// e = alpha Gamma - beta^r u_r
+__device__ __forceinline__ double energy(double a, const double* z) {
+  Met m;
+  metric(a, z[0], z[1], m);
+  double ur = z[3], ut = z[4], up = z[5];
+  double q = m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
+             2.0 * m.irp * ur * up;
+  return m.alpha * sqrt(1.0 + q) - m.betar * ur;
+}
+
+// ---------------------------------------------------------------- gather
+struct GridView {
+  int nr, nth;
+  double a, r_in, th0, dth, inv_dlnr, inv_dth;
+  const double *rn, *rh, *tn, *th;  // coordinates
+  const double *idrn, *idrh;        // 1/(rn[i+1]-rn[i]), 1/(rh[i+1]-rh[i])
+};
+
+struct FieldView {  // densitized FP32 components at their Yee points
+  const float *Dr, *Dt, *Dp, *Br, *Bt, *Bp;
+};
+
+inline GridView make_grid_view(const grpic_ctx* c) {
+  GridView g;
+  g.nr = c->nr;
+  g.nth = c->nth;
+  g.a = c->cfg.a;
+  g.r_in = c->cfg.r_in;
+  g.th0 = c->cfg.theta0;
+  g.dth = c->dth;
+  g.inv_dlnr = c->dlnr > 0 ? 1.0 / c->dlnr : 0.0;
+  g.inv_dth = c->dth > 0 ? 1.0 / c->dth : 0.0;
+  g.rn = c->rn;
+  g.rh = c->rh;
+  g.tn = c->tn;
+  g.th = c->th;
+  g.idrn = c->idrn;
+  g.idrh = c->idrh;
+  return g;
+}
+
+// cell index p in [0, n-2] with x[p] <= v < x[p+1] (clamped), from a first
+// estimate that may be off by one
+__device__ __forceinline__ int refine(const double* x, int n, double v, int p) {
+  p = p < 0 ? 0 : (p > n - 2 ? n - 2 : p);
+  if (p > 0 && v < x[p]) --p;
+  else if (p < n - 2 && v >= x[p + 1]) ++p;
+  return p;
+}
+
+__device__ __forceinline__ double clamp01(double f) {
+  return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+}
+
+struct Stencil {
+  int pn, ph, qn, qh;       // cell indices on node / half sub-grids
+  double frn, frh, ftn, fth;  // fractions
+};
+
+__device__ __forceinline__ void locate(const GridView& g, double r, double th,
+                                       Stencil& S) {
+  double lr = log(r / g.r_in) * g.inv_dlnr;
+  double lt = (th - g.th0) * g.inv_dth;
+  int pn = refine(g.rn, g.nr + 1, r, (int)floor(lr));
+  int ph = refine(g.rh, g.nr, r, (int)floor(lr - 0.5));
+  int qn = refine(g.tn, g.nth + 1, th, (int)floor(lt));
+  int qh = refine(g.th, g.nth, th, (int)floor(lt - 0.5));
+  S.pn = pn;
+  S.ph = ph;
+  S.qn = qn;
+  S.qh = qh;
+  S.frn = clamp01((r - g.rn[pn]) * g.idrn[pn]);
+  S.frh = clamp01((r - g.rh[ph]) * g.idrh[ph]);
+  S.ftn = clamp01((th - g.tn[qn]) * g.inv_dth);
+  S.fth = clamp01((th - g.th[qh]) * g.inv_dth);
+}
+
+__device__ __forceinline__ double bilin(const float* A, int nR, int p, int q,
+                                        double fr, double ft) {
+  const float* row0 = A + (long)q * nR + p;
+  const float* row1 = row0 + nR;
+  double v00 = row0[0], v10 = row0[1], v01 = row1[0], v11 = row1[1];
+  double b0 = v00 + fr * (v10 - v00);
+  double b1 = v01 + fr * (v11 - v01);
+  return b0 + ft * (b1 - b0);
+}
+
+// D^i, B^i at (r, theta): sum_c w_c (sqrt(g) F)_c / sqrt(g)(x)
+__device__ __forceinline__ void gather(const GridView& g, const FieldView& F,
+                                       double r, double th, double isg,
+                                       double* D, double* B) {
+  Stencil S;
+  locate(g, r, th, S);
+  int nrn = g.nr + 1, nrh = g.nr;
+  D[0] = bilin(F.Dr, nrh, S.ph, S.qn, S.frh, S.ftn) * isg;
+  D[1] = bilin(F.Dt, nrn, S.pn, S.qh, S.frn, S.fth) * isg;
+  D[2] = bilin(F.Dp, nrn, S.pn, S.qn, S.frn, S.ftn) * isg;
+  B[0] = bilin(F.Br, nrn, S.pn, S.qh, S.frn, S.fth) * isg;
+  B[1] = bilin(F.Bt, nrh, S.ph, S.qn, S.frh, S.ftn) * isg;
+  B[2] = bilin(F.Bp, nrh, S.ph, S.qh, S.frh, S.fth) * isg;
+}
+
+// ------------------------------------------------------- equations of motion
+// f = (dx^i/dt, du_i/dt); *pw = (q/m) E_i dx^i/dt with
+// E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei).
+__device__ __forceinline__ void rhs(double qm, const double* z, const Met& m,
+                                    const DMet& d, const double* D,
+                                    const double* B, double* f, double* pw) {
+  double ur = z[3], ut = z[4], up = z[5];
+  double Ur = m.irr * ur + m.irp * up;
+  double Ut = m.itt * ut;
+  double Up = m.irp * ur + m.ipp * up;
+  double G = sqrt(1.0 + ur * Ur + ut * Ut + up * Up);
+  double iG = rcp(G);
+  double aiG = m.alpha * iG;
+  f[0] = aiG * Ur - m.betar;
+  f[1] = aiG * Ut;
+  f[2] = aiG * Up;
+  double half_aiG = 0.5 * aiG;
+  double q_r = ur * ur * d.drr[0] + ut * ut * d.dtt[0] + up * up * d.dpp[0] +
+               2.0 * ur * up * d.drp[0];
+  double q_t = ur * ur * d.drr[1] + ut * ut * d.dtt[1] + up * up * d.dpp[1] +
+               2.0 * ur * up * d.drp[1];
+  double gr = -G * d.da[0] + ur * d.db[0] - half_aiG * q_r;
+  double gt = -G * d.da[1] + ur * d.db[1] - half_aiG * q_t;
+  if (qm != 0.0) {
+    double Dl_r = m.grr * D[0] + m.grp * D[2];
+    double Dl_t = m.gtt * D[1];
+    double Dl_p = m.grp * D[0] + m.gpp * D[2];
+    double sgiG = m.sg * iG;
+    double cr = Ut * B[2] - Up * B[1];
+    double ct = Up * B[0] - Ur * B[2];
+    double cp = Ur * B[1] - Ut * B[0];
+    double qa = qm * m.alpha;
+    f[3] = gr + qa * (Dl_r + sgiG * cr);
+    f[4] = gt + qa * (Dl_t + sgiG * ct);
+    f[5] = qa * (Dl_p + sgiG * cp);
+    double sgb = m.sg * m.betar;
+    double Er = m.alpha * Dl_r;
+    double Et = m.alpha * Dl_t - sgb * B[2];
+    double Ep = m.alpha * Dl_p + sgb * B[1];
+    *pw = qm * (Er * f[0] + Et * f[1] + Ep * f[2]);
+  } else {
+    f[3] = gr;
+    f[4] = gt;
+    f[5] = 0.0;
+    *pw = 0.0;
+  }
+}
+
+}  // namespace grpic

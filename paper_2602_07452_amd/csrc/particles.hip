@@ -1,0 +1,264 @@
+// particles.hip -- particle initial data, tile sort and small utilities.
+//
+// Initial data: counter-based SplitMix64 draws (Steele, Lea & Flood 2014),
+// draw k of stream s uses counter s * 256 + k.  Positions uniform in proper
+// volume by rejection against r^2 sin(theta) proposals (at most 64 tries),
+// FIDO-frame momenta (isotropic |u| ~ U[0, p0], or Maxwell-Juettner by
+// inverting a tabulated cumulative distribution), mapped to covariant u_i
+// with the Cholesky factor of gamma_ij (order r, theta, phi).
+//
+// Tile sort: counting sort of the particles by (32 x 32 by default) node-cell
+// tile, dead particles last; keeps a block's particles in a few cells for
+// the gather and the deposit.
+#include "deposit_device.hpp"
+
+namespace grpic {
+
+// ------------------------------------------------------------------- fill
+__global__ void k_fill(uint32_t* p, long n) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
+}
+
+void launch_fill(grpic_ctx* c, void* p, size_t bytes) {
+  long n = (long)(bytes / 4);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
+                     (uint32_t*)p, n);
+  GRPIC_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ SplitMix64
+__device__ __forceinline__ double splitmix_u01(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double draw(uint64_t seed, long stream, int k) {
+  return splitmix_u01(seed, (uint64_t)stream * 256ull + (uint64_t)k);
+}
+
+struct InitArgs {
+  ParticleView p;
+  grpic_init_spec s;
+  double a;
+  const double* mj;  // cumulative table, mj_k + 1 entries
+  int mj_k;
+  double mj_h;
+};
+
+__global__ void k_init(InitArgs A) {
+  long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= A.s.n) return;
+  const grpic_init_spec& s = A.s;
+  const double a = A.a;
+  double z[6];
+  int8_t qm;
+  if (s.kind == GRPIC_INIT_ORBITS) {
+    double r = s.r0 + (s.r1 - s.r0) * draw(s.seed, id, 0);
+    double th = s.t0 + (s.t1 - s.t0) * draw(s.seed, id, 1);
+    double E = (1.0 - 2.0 / r) / sqrt(1.0 - 3.0 / r);
+    double L = sqrt(r) / sqrt(1.0 - 3.0 / r);
+    z[0] = r;
+    z[1] = th;
+    z[2] = 0.0;
+    z[3] = 2.0 * E / (r - 2.0);
+    if (id & 1) z[3] += -s.p0 + 2.0 * s.p0 * draw(s.seed, id, 2);
+    z[4] = 0.0;
+    z[5] = L * sin(th);
+    qm = 0;
+  } else {
+    long pid = (s.kind == GRPIC_INIT_SHELL_MJ) ? id / 2 : id;
+    double C = (1.0 + a * a / (s.r0 * s.r0)) * sqrt(1.0 + 2.0 / s.r0);
+    double c0 = cos(s.t0), c1 = cos(s.t1);
+    double r = s.r0, th = s.t0;
+    double r03 = s.r0 * s.r0 * s.r0, r13 = s.r1 * s.r1 * s.r1;
+    for (int t = 0; t < 64; ++t) {
+      double u1 = draw(s.seed, pid, 3 * t), u2 = draw(s.seed, pid, 3 * t + 1),
+             u3 = draw(s.seed, pid, 3 * t + 2);
+      r = cbrt(r03 + u1 * (r13 - r03));
+      th = acos(c0 - u2 * (c0 - c1));
+      double c = cos(th);
+      double rho2 = r * r + a * a * c * c;
+      double ratio = rho2 / (r * r) * sqrt(1.0 + 2.0 * r / rho2);
+      if (u3 * C < ratio) break;
+    }
+    z[0] = r;
+    z[1] = th;
+    z[2] = 2.0 * kPi * draw(s.seed, pid, 192);
+    double mag;
+    if (s.kind == GRPIC_INIT_SHELL_MJ) {
+      double x = draw(s.seed, id, 200);
+      int lo = 0, hi = A.mj_k;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (A.mj[mid] <= x) lo = mid;
+        else hi = mid;
+      }
+      double dc = A.mj[lo + 1] - A.mj[lo];
+      double f = dc > 0.0 ? (x - A.mj[lo]) / dc : 0.0;
+      mag = (lo + f) * A.mj_h;
+    } else {
+      mag = s.p0 * draw(s.seed, id, 200);
+    }
+    double mu = 2.0 * draw(s.seed, id, 201) - 1.0;
+    double az = 2.0 * kPi * draw(s.seed, id, 202);
+    double sn = sqrt(1.0 - mu * mu);
+    double fr = mag * mu, ft = mag * sn * cos(az), fp = mag * sn * sin(az);
+    Met m;
+    metric(a, r, th, m);
+    double Lrr = sqrt(m.grr), Ltt = sqrt(m.gtt), Lpr = m.grp / Lrr;
+    double Lpp = sqrt(m.gpp - Lpr * Lpr);
+    z[3] = Lrr * fr;
+    z[4] = Ltt * ft;
+    z[5] = Lpr * fr + Lpp * fp;
+    qm = (id & 1) ? -1 : 1;
+  }
+  ParticleView& P = A.p;
+  P.r[id] = z[0];
+  P.th[id] = z[1];
+  P.ph[id] = z[2];
+  P.ur[id] = z[3];
+  P.uth[id] = z[4];
+  P.uph[id] = z[5];
+  P.qm[id] = qm;
+  P.w[id] = s.w;
+  P.H0[id] = energy(a, z);
+  P.herr[id] = 0.0;
+  P.flags[id] = GRPIC_FLAG_ALIVE;
+  P.iters[id] = 0;
+  P.id[id] = (uint32_t)id;
+}
+
+void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,
+                           const double* mj_table, int mj_k, double mj_h) {
+  InitArgs A;
+  A.p = c->pv;
+  A.s = *s;
+  A.a = c->cfg.a;
+  A.mj = mj_table;
+  A.mj_k = mj_k;
+  A.mj_h = mj_h;
+  hipLaunchKernelGGL(k_init, dim3(grid_for(s->n, 256)), dim3(256), 0,
+                     c->stream, A);
+  GRPIC_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------------- tile sort
+struct SortArgs {
+  GridView g;
+  ParticleView p, q;  // source, destination
+  int tile_r, tile_th, ntr, ntiles;
+  int* count;
+  int* offset;
+};
+
+__device__ __forceinline__ int tile_key(const SortArgs& A, long k) {
+  if (!(A.p.flags[k] & GRPIC_FLAG_ALIVE)) return A.ntiles;
+  int p, q;
+  node_cell(A.g, A.p.r[k], A.p.th[k], p, q);
+  return (q / A.tile_th) * A.ntr + p / A.tile_r;
+}
+
+__global__ void k_tile_count(SortArgs A) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.p.n) return;
+  atomicAdd(&A.count[tile_key(A, k)], 1);
+}
+
+// exclusive scan of ntiles + 1 counts in one block
+__global__ void k_tile_scan(int* count, int* offset, int n) {
+  __shared__ int part[256];
+  int t = threadIdx.x;
+  int per = (n + 255) / 256;
+  int lo = t * per, hi = min(n, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += count[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int i = 0; i < 256; ++i) {
+      int v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int acc = part[t];
+  for (int i = lo; i < hi; ++i) {
+    offset[i] = acc;
+    acc += count[i];
+    count[i] = 0;
+  }
+}
+
+__global__ void k_tile_scatter(SortArgs A) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.p.n) return;
+  int key = tile_key(A, k);
+  long d = atomicAdd(&A.offset[key], 1);
+  const ParticleView &S = A.p, &D = A.q;
+  D.r[d] = S.r[k];
+  D.th[d] = S.th[k];
+  D.ph[d] = S.ph[k];
+  D.ur[d] = S.ur[k];
+  D.uth[d] = S.uth[k];
+  D.uph[d] = S.uph[k];
+  D.H0[d] = S.H0[k];
+  D.herr[d] = S.herr[k];
+  D.w[d] = S.w[k];
+  D.qm[d] = S.qm[k];
+  D.flags[d] = S.flags[k];
+  D.iters[d] = S.iters[k];
+  D.id[d] = S.id[k];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) D.W[c][d] = S.W[c][k];
+  D.cell[d] = S.cell[k];
+}
+
+void launch_sort(grpic_ctx* c) {
+  if (c->n == 0 || c->nr == 0) return;
+  hipEvent_t ev;
+  time_begin(c, GRPIC_K_SORT, &ev);
+  SortArgs A;
+  A.g = make_grid_view(c);
+  A.p = c->pv;
+  A.p.n = c->n;
+  A.q = c->alt;
+  A.tile_r = c->cfg.tile_r;
+  A.tile_th = c->cfg.tile_th;
+  A.ntr = (c->nr + A.tile_r - 1) / A.tile_r;
+  A.ntiles = c->ntiles;
+  A.count = c->tile_count;
+  A.offset = c->tile_offset;
+  dim3 g(grid_for(c->n, 256)), b(256);
+  hipLaunchKernelGGL(k_tile_count, g, b, 0, c->stream, A);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, c->stream,
+                     c->tile_count, c->tile_offset, c->ntiles + 1);
+  hipLaunchKernelGGL(k_tile_scatter, g, b, 0, c->stream, A);
+  GRPIC_HIP(hipGetLastError());
+  ParticleView& P = c->pv;
+  ParticleView& Q = c->alt;
+  std::swap(P.r, Q.r);
+  std::swap(P.th, Q.th);
+  std::swap(P.ph, Q.ph);
+  std::swap(P.ur, Q.ur);
+  std::swap(P.uth, Q.uth);
+  std::swap(P.uph, Q.uph);
+  std::swap(P.H0, Q.H0);
+  std::swap(P.herr, Q.herr);
+  std::swap(P.w, Q.w);
+  std::swap(P.qm, Q.qm);
+  std::swap(P.flags, Q.flags);
+  std::swap(P.iters, Q.iters);
+  std::swap(P.id, Q.id);
+  for (int q = 0; q < 4; ++q) std::swap(P.W[q], Q.W[q]);
+  std::swap(P.cell, Q.cell);
+  time_end(c, GRPIC_K_SORT, ev);
+}
+
+}  // namespace grpic

@@ -1,0 +1,530 @@
+// push.hip -- particle push of the GRPIC step (sub-step 5 of Sec. 2.1):
+// field gather, RK4 (Sec. 2.2.1), the Hyb1/Hyb2 energy switch (Sec. 3.1.2),
+// the implicit midpoint rule (Sec. 2.2.2) and the discrete-gradient
+// Hamiltonian scheme (Sec. 2.2.3, App. D), particle boundary conditions
+// (Sec. 2.5) and the deposit weights of the pushed positions (Sec. 2.3).
+//
+// Two passes per step:
+//  * k_push_explicit: one thread per particle.  RK4 with fields re-gathered
+//    at every stage; the switch either accepts the step or appends the
+//    particle to the implicit queue (wave ballot + one atomic per wave).
+//  * k_push_implicit: persistent kernel; each wave takes 64 queue entries
+//    at a time from a device cursor until the queue is drained.
+#include "deposit_device.hpp"
+
+namespace grpic {
+
+enum : uint8_t {
+  F_ALIVE = GRPIC_FLAG_ALIVE,
+  F_IMPLICIT = GRPIC_FLAG_IMPLICIT,
+  F_NOCONV = GRPIC_FLAG_NOCONV,
+  F_REMOVED = GRPIC_FLAG_REMOVED,
+  F_REFLECTED = GRPIC_FLAG_REFLECTED
+};
+
+struct PushArgs {
+  GridView g;
+  FieldView f;
+  ParticleView p;
+  double a, dt, thr, tol, ham_eps, r_min, r_max, th_lo, th_hi;
+  int pusher, guess, kmax, reflect;
+  double* gz[6];
+  int* queue;
+  Stats* st;
+};
+
+struct LocalStats {
+  unsigned int herr_hist[kHistBins];
+  unsigned int iter_hist[kHistBins];
+  unsigned int implicit_steps, noconv, removed, reflected, alive;
+};
+
+__device__ __forceinline__ void stats_init(LocalStats& s) {
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) {
+    s.herr_hist[i] = 0;
+    s.iter_hist[i] = 0;
+  }
+  if (threadIdx.x == 0)
+    s.implicit_steps = s.noconv = s.removed = s.reflected = s.alive = 0;
+}
+
+__device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* g) {
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) {
+    if (s.herr_hist[i]) atomicAdd(&g->herr_hist[i], (unsigned long long)s.herr_hist[i]);
+    if (s.iter_hist[i]) atomicAdd(&g->iter_hist[i], (unsigned long long)s.iter_hist[i]);
+  }
+  if (threadIdx.x == 0) {
+    if (s.implicit_steps) atomicAdd(&g->implicit_steps, (unsigned long long)s.implicit_steps);
+    if (s.noconv) atomicAdd(&g->noconv, (unsigned long long)s.noconv);
+    if (s.removed) atomicAdd(&g->removed, (unsigned long long)s.removed);
+    if (s.reflected) atomicAdd(&g->reflected, (unsigned long long)s.reflected);
+    if (s.alive) atomicAdd(&g->alive, (unsigned long long)s.alive);
+  }
+}
+
+// --------------------------------------------------------------- F(z)
+template <bool GRID>
+__device__ __forceinline__ void eval(const PushArgs& A, double qm,
+                                     const double* z, double* f, double* pw) {
+  Met m;
+  DMet d;
+  metric_d(A.a, z[0], z[1], m, d);
+  double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
+  if (GRID && qm != 0.0) gather(A.g, A.f, z[0], z[1], rcp(m.sg), D, B);
+  rhs(qm, z, m, d, D, B, f, pw);
+}
+
+template <bool GRID>
+__device__ __forceinline__ void rk4(const PushArgs& A, double qm,
+                                    const double* z, double* out, double* Wq) {
+  const double dt = A.dt, hdt = 0.5 * A.dt;
+  double k[6], acc[6], y[6], p, pacc;
+  eval<GRID>(A, qm, z, k, &p);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    acc[i] = k[i];
+    y[i] = z[i] + hdt * k[i];
+  }
+  pacc = p;
+  eval<GRID>(A, qm, y, k, &p);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    acc[i] += 2.0 * k[i];
+    y[i] = z[i] + hdt * k[i];
+  }
+  pacc += 2.0 * p;
+  eval<GRID>(A, qm, y, k, &p);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    acc[i] += 2.0 * k[i];
+    y[i] = z[i] + dt * k[i];
+  }
+  pacc += 2.0 * p;
+  eval<GRID>(A, qm, y, k, &p);
+  const double c6 = dt / 6.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[i] = z[i] + c6 * (acc[i] + k[i]);
+  *Wq = c6 * (pacc + p);
+}
+
+__device__ __forceinline__ bool small_change(const double* zn, const double* zo,
+                                             double tol) {
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double sc = fmax(fabs(zn[i]), 1.0);
+    m = fmax(m, fabs(zn[i] - zo[i]) / sc);
+  }
+  return m <= tol;
+}
+
+// implicit midpoint rule by fixed-point iteration; zk: guess in, result out
+template <bool GRID>
+__device__ int imr(const PushArgs& A, double qm, const double* z, double* zk,
+                   double* Wq) {
+  double p = 0.0;
+  for (int k = 1; k <= A.kmax; ++k) {
+    double zm[6], f[6], zn[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zm[i] = 0.5 * (z[i] + zk[i]);
+    eval<GRID>(A, qm, zm, f, &p);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zn[i] = z[i] + A.dt * f[i];
+    bool c = small_change(zn, zk, A.tol);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zk[i] = zn[i];
+    if (c) {
+      *Wq = A.dt * p;
+      return k;
+    }
+  }
+  *Wq = A.dt * p;
+  return -A.kmax;
+}
+
+// ------------------------------------------- discrete-gradient scheme (DG)
+// Variables 0 r, 1 theta, 2 phi, 3 u_r, 4 u_theta, 5 u_phi.  Six orderings
+// (three cyclic orders with x before u and their reverses); at most four
+// distinct positions (r^n or r^{n+1}) x (theta^n or theta^{n+1}) occur.
+// Position quotients of the metric are cancellation-free divided
+// differences (metric_dd); below |dx| = eps the analytic derivative at the
+// midpoint replaces them.
+__constant__ int8_t kDGOrder[6][6] = {{0, 3, 1, 4, 2, 5}, {1, 4, 2, 5, 0, 3},
+                                      {2, 5, 0, 3, 1, 4}, {5, 2, 4, 1, 3, 0},
+                                      {3, 0, 5, 2, 4, 1}, {4, 1, 3, 0, 5, 2}};
+
+__device__ __forceinline__ double lorentz(const Met& m, double ur, double ut,
+                                          double up) {
+  return sqrt(1.0 + m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
+              2.0 * m.irp * ur * up);
+}
+
+__device__ int ham_dg(const PushArgs& A, const double* z, double* zk) {
+  for (int k = 1; k <= A.kmax; ++k) {
+    Met M[4];  // index: bit0 = r updated, bit1 = theta updated
+    metric(A.a, z[0], z[1], M[0]);
+    metric(A.a, zk[0], z[1], M[1]);
+    metric(A.a, z[0], zk[1], M[2]);
+    metric(A.a, zk[0], zk[1], M[3]);
+    double grad[6] = {0, 0, 0, 0, 0, 0};
+    for (int o = 0; o < 6; ++o) {
+      int mask = 0;  // bit v set: variable v already at level n+1
+      for (int s = 0; s < 6; ++s) {
+        int v = kDGOrder[o][s];
+        double ur = (mask & 8) ? zk[3] : z[3];
+        double ut = (mask & 16) ? zk[4] : z[4];
+        double up = (mask & 32) ? zk[5] : z[5];
+        double q = 0.0;
+        if (v >= 3) {
+          const Met& m = M[mask & 3];
+          double ur1 = v == 3 ? zk[3] : ur, ut1 = v == 4 ? zk[4] : ut,
+                 up1 = v == 5 ? zk[5] : up;
+          double G0 = lorentz(m, ur, ut, up), G1 = lorentz(m, ur1, ut1, up1);
+          double num;
+          if (v == 3)
+            num = m.irr * (ur1 + ur) + 2.0 * m.irp * up;
+          else if (v == 4)
+            num = m.itt * (ut1 + ut);
+          else
+            num = m.ipp * (up1 + up) + 2.0 * m.irp * ur;
+          q = m.alpha * num / (G0 + G1) - (v == 3 ? m.betar : 0.0);
+        } else if (v < 2) {
+          const Met& m0 = M[mask & 3];
+          const Met& m1 = M[(mask | (1 << v)) & 3];
+          double G0 = lorentz(m0, ur, ut, up), G1 = lorentz(m1, ur, ut, up);
+          double dx = zk[v] - z[v];
+          double qa, qb, qrr, qtt, qpp, qrp;
+          if (fabs(dx) >= A.ham_eps) {
+            double q6[6];
+            double r0 = (mask & 1) ? zk[0] : z[0];
+            double r1 = v == 0 ? zk[0] : r0;
+            metric_dd(A.a, v, r0, r1, dx, m0, m1, q6);
+            qa = q6[0];
+            qb = q6[1];
+            qrr = q6[2];
+            qtt = q6[3];
+            qpp = q6[4];
+            qrp = q6[5];
+          } else {
+            double rr = v == 0 ? 0.5 * (z[0] + zk[0]) : ((mask & 1) ? zk[0] : z[0]);
+            double tt = v == 1 ? 0.5 * (z[1] + zk[1]) : ((mask & 2) ? zk[1] : z[1]);
+            Met mm;
+            DMet d;
+            metric_d(A.a, rr, tt, mm, d);
+            qa = d.da[v];
+            qb = d.db[v];
+            qrr = d.drr[v];
+            qtt = d.dtt[v];
+            qpp = d.dpp[v];
+            qrp = d.drp[v];
+          }
+          double quad = qrr * ur * ur + qtt * ut * ut + qpp * up * up +
+                        2.0 * qrp * ur * up;
+          q = 0.5 * (G0 + G1) * qa + 0.5 * (m0.alpha + m1.alpha) * quad / (G0 + G1) -
+              ur * qb;
+        }
+        grad[v] += q * (1.0 / 6.0);
+        mask |= 1 << v;
+      }
+    }
+    double zn[6];
+    zn[0] = z[0] + A.dt * grad[3];
+    zn[1] = z[1] + A.dt * grad[4];
+    zn[2] = z[2] + A.dt * grad[5];
+    zn[3] = z[3] - A.dt * grad[0];
+    zn[4] = z[4] - A.dt * grad[1];
+    zn[5] = z[5] - A.dt * grad[2];
+    bool c = small_change(zn, zk, A.tol);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zk[i] = zn[i];
+    if (c) return k;
+  }
+  return -A.kmax;
+}
+
+// ----------------------------------------------------------- switch value
+// neutral: |e - H0| / |H0|; charged: |e' - e - W| / |e| (W: the scheme's
+// quadrature of (q/m) E_i dx^i/dt)
+__device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
+                                               double H0, double e0,
+                                               const double* zn, double Wq) {
+  double e1 = energy(A.a, zn);
+  if (qm == 0.0) return fabs(e1 - H0) / fabs(H0);
+  return fabs(e1 - e0 - Wq) / fabs(e0);
+}
+
+__device__ __forceinline__ int herr_bin(double v) {
+  if (!(v > 0.0)) return 0;
+  int b = (int)floor(2.0 * (log10(v) + 30.0));
+  return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
+}
+
+// write the step result, apply the particle boundary conditions and (for a
+// deposit) store the old position and the weights of the new one
+template <bool EVOLVE>
+__device__ void finalize(const PushArgs& A, long k, const double* z,
+                         double* out, double herr, int iters, uint8_t fl,
+                         LocalStats& ls) {
+  const ParticleView& P = A.p;
+  if (out[0] < A.r_min || out[0] > A.r_max) {
+    fl = F_REMOVED;
+    atomicAdd(&ls.removed, 1u);
+  } else if (A.reflect) {
+    if (out[1] < A.th_lo) {
+      out[1] = 2.0 * A.th_lo - out[1];
+      out[4] = -out[4];
+      fl |= F_REFLECTED;
+      atomicAdd(&ls.reflected, 1u);
+    } else if (out[1] > A.th_hi) {
+      out[1] = 2.0 * A.th_hi - out[1];
+      out[4] = -out[4];
+      fl |= F_REFLECTED;
+      atomicAdd(&ls.reflected, 1u);
+    }
+  }
+  P.r[k] = out[0];
+  P.th[k] = out[1];
+  P.ph[k] = out[2];
+  P.ur[k] = out[3];
+  P.uth[k] = out[4];
+  P.uph[k] = out[5];
+  P.herr[k] = herr;
+  P.flags[k] = fl;
+  P.iters[k] = (uint8_t)iters;
+  if (fl & F_ALIVE) {
+    atomicAdd(&ls.alive, 1u);
+    atomicAdd(&ls.herr_hist[herr_bin(herr)], 1u);
+  }
+  if (fl & F_IMPLICIT) {
+    atomicAdd(&ls.implicit_steps, 1u);
+    atomicAdd(&ls.iter_hist[iters < kHistBins ? iters : kHistBins - 1], 1u);
+  }
+  if (fl & F_NOCONV) atomicAdd(&ls.noconv, 1u);
+  if (EVOLVE) {
+    P.r_old[k] = z[0];
+    P.th_old[k] = z[1];
+    P.dphi[k] = out[2] - z[2];
+    if (fl & F_ALIVE) {
+      int p, q;
+      node_cell(A.g, out[0], out[1], p, q);
+      double W[4];
+      dep_weights(A.g, out[0], out[1], p, q, W);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) P.Wn[c][k] = W[c];
+      P.celln[k] = q * A.g.nr + p;
+    }
+  }
+}
+
+__device__ __forceinline__ void load_z(const ParticleView& P, long k,
+                                       double* z) {
+  z[0] = P.r[k];
+  z[1] = P.th[k];
+  z[2] = P.ph[k];
+  z[3] = P.ur[k];
+  z[4] = P.uth[k];
+  z[5] = P.uph[k];
+}
+
+// ------------------------------------------------------- explicit pass
+template <bool GRID, bool EVOLVE>
+__global__ __launch_bounds__(256) void k_push_explicit(PushArgs A) {
+  __shared__ LocalStats ls;
+  stats_init(ls);
+  __syncthreads();
+  const ParticleView& P = A.p;
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = k < P.n && (P.flags[k] & F_ALIVE);
+  bool enq = false;
+  double trial[6];
+  if (act) {
+    double z[6];
+    load_z(P, k, z);
+    double qm = (double)P.qm[k];
+    if (A.pusher == GRPIC_PUSH_IMR || A.pusher == GRPIC_PUSH_HAM) {
+      enq = true;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
+    } else {
+      double Wq;
+      rk4<GRID>(A, qm, z, trial, &Wq);
+      double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
+      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq);
+      bool accept = true;
+      if (A.pusher == GRPIC_PUSH_HYB2) {
+        accept = v < A.thr;
+      } else if (A.pusher == GRPIC_PUSH_HYB1) {
+        double prev = P.herr[k];
+        accept = (v - prev) / (A.dt * fmax(prev, 0x1p-52)) < A.thr;
+      }
+      if (accept)
+        finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls);
+      else
+        enq = true;
+    }
+  }
+  // append the rejected particles to the implicit queue
+  unsigned long long mask = __ballot(enq);
+  if (mask) {
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)mask) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&A.st->queue_count, (unsigned)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (enq) {
+      unsigned slot = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+      A.queue[slot] = (int)k;
+      if (A.guess == GRPIC_GUESS_RK4) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
+      }
+    }
+  }
+  __syncthreads();
+  stats_flush(ls, A.st);
+}
+
+// ------------------------------------------------------- implicit pass
+template <bool GRID, bool EVOLVE>
+__global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
+  __shared__ LocalStats ls;
+  stats_init(ls);
+  __syncthreads();
+  const ParticleView& P = A.p;
+  const int lane = threadIdx.x & 63;
+  const unsigned qn = A.st->queue_count;
+  for (;;) {
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(&A.st->work_counter, 64u);
+    base = __shfl(base, 0, 64);
+    if (base >= qn) break;
+    unsigned slot = base + lane;
+    if (slot < qn) {
+      long k = A.queue[slot];
+      double z[6], zk[6];
+      load_z(P, k, z);
+      double qm = (double)P.qm[k];
+      if (A.guess == GRPIC_GUESS_PLAIN) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zk[i] = z[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zk[i] = A.gz[i][slot];
+      }
+      int it;
+      double Wq = 0.0;
+      if (qm == 0.0 && A.pusher != GRPIC_PUSH_IMR)
+        it = ham_dg(A, z, zk);
+      else
+        it = imr<GRID>(A, qm, z, zk, &Wq);
+      uint8_t fl = F_ALIVE | F_IMPLICIT;
+      if (it < 0) {
+        fl |= F_NOCONV;
+        it = -it;
+      }
+      double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
+      double v = switch_value(A, qm, P.H0[k], e0, zk, Wq);
+      finalize<EVOLVE>(A, k, z, zk, v, it, fl, ls);
+    }
+  }
+  __syncthreads();
+  stats_flush(ls, A.st);
+}
+
+__global__ void k_reset_step(Stats* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->queue_count = 0;
+    st->work_counter = 0;
+    st->guess_counter = 0;
+    for (int i = 0; i < kHistBins; ++i) st->herr_hist[i] = 0;
+    st->alive = 0;
+  }
+}
+
+static PushArgs make_args(grpic_ctx* c) {
+  PushArgs A;
+  A.g = make_grid_view(c);
+  A.f.Dr = c->D[2].c[0];
+  A.f.Dt = c->D[2].c[1];
+  A.f.Dp = c->D[2].c[2];
+  A.f.Br = c->B[2].c[0];
+  A.f.Bt = c->B[2].c[1];
+  A.f.Bp = c->B[2].c[2];
+  A.p = c->pv;
+  A.p.n = c->n;
+  A.a = c->cfg.a;
+  A.dt = c->cfg.dt;
+  A.thr = c->cfg.hyb_threshold;
+  A.tol = c->cfg.tol;
+  A.ham_eps = c->cfg.ham_eps;
+  A.r_min = c->cfg.r_remove_in;
+  A.r_max = c->cfg.r_remove_out;
+  A.th_lo = c->cfg.theta0;
+  A.th_hi = kPi - c->cfg.theta0;
+  A.pusher = c->cfg.pusher;
+  A.guess = c->cfg.guess;
+  A.kmax = c->cfg.kmax;
+  A.reflect = c->cfg.reflect;
+  for (int i = 0; i < 6; ++i) A.gz[i] = c->gz[i];
+  A.queue = c->queue;
+  A.st = c->stats;
+  return A;
+}
+
+template <bool GRID, bool EVOLVE>
+static void push_impl(grpic_ctx* c, const PushArgs& A) {
+  int block = 256;
+  hipEvent_t ev;
+  time_begin(c, GRPIC_K_PUSH, &ev);
+  hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE>), dim3(grid_for(c->n, block)),
+                     dim3(block), 0, c->stream, A);
+  GRPIC_HIP(hipGetLastError());
+  time_end(c, GRPIC_K_PUSH, ev);
+  bool implicit = c->cfg.pusher != GRPIC_PUSH_RK4;
+  if (!implicit) return;
+  if (c->cfg.guess == GRPIC_GUESS_MLP) launch_guess(c);
+  int dev_cus = c->num_cus;
+  int waves = c->cfg.persistent_waves > 0 ? c->cfg.persistent_waves : 8;
+  unsigned blocks = (unsigned)((long)dev_cus * waves / 4);
+  long need = (c->n + 255) / 256;
+  if ((long)blocks > need) blocks = (unsigned)(need < 1 ? 1 : need);
+  time_begin(c, GRPIC_K_IMPLICIT, &ev);
+  hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE>), dim3(blocks), dim3(256), 0,
+                     c->stream, A);
+  GRPIC_HIP(hipGetLastError());
+  time_end(c, GRPIC_K_IMPLICIT, ev);
+}
+
+void launch_push(grpic_ctx* c) {
+  if (c->n == 0) return;
+  hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(64), 0, c->stream, c->stats);
+  GRPIC_HIP(hipGetLastError());
+  PushArgs A = make_args(c);
+  int mode = c->cfg.field_mode;
+  if (mode == GRPIC_FIELDS_NONE)
+    push_impl<false, false>(c, A);
+  else if (mode == GRPIC_FIELDS_STATIC)
+    push_impl<true, false>(c, A);
+  else
+    push_impl<true, true>(c, A);
+}
+
+// ------------------------------------------------------- initial energy
+__global__ void k_energy_H0(ParticleView P, double a) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  double z[6];
+  load_z(P, k, z);
+  P.H0[k] = energy(a, z);
+}
+
+void launch_energy_H0(grpic_ctx* c) {
+  if (c->n == 0) return;
+  ParticleView P = c->pv;
+  P.n = c->n;
+  hipLaunchKernelGGL(k_energy_H0, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, P, c->cfg.a);
+  GRPIC_HIP(hipGetLastError());
+}
+
+}  // namespace grpic

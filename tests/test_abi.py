@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point of include/grpic.h
+(no compute calls: runs without a GPU)."""
+import ctypes as C
+import subprocess
+
+import pytest
+
+import paper_2602_07452_amd as G
+
+
+def test_library_exports_every_declared_symbol():
+    L = G.lib()
+    names = G.exported_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_config_default():
+    cfg = G.config_default()
+    assert cfg.tol == 1e-13 and cfg.kmax == 50 and cfg.tile_r == 32
+    assert abs(cfg.theta0 - 3.141592653589793 / 200) < 1e-15
+
+
+@pytest.mark.parametrize("cls,cname", [(G.Config, "grpic_config"),
+                                       (G.InitSpec, "grpic_init_spec"),
+                                       (G.Diag, "grpic_diag")])
+def test_struct_layout_matches_header(cls, cname, tmp_path):
+    """The ctypes mirrors have the C structs' size and field offsets."""
+    fields = [f[0] for f in cls._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{G.HEADER}"',
+           'int main(void) {', f'printf("%zu\\n", sizeof({cname}));']
+    src += [f'printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
+    src += ['return 0; }']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-o", str(exe), str(c)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == C.sizeof(cls)
+    assert vals[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_cfl_limit_host_side():
+    cfg = G.config_default(a=0.99, nr=64, nth=64, r_in=1.03, r_out=20.0)
+    dt = G.cfl_dt(cfg)
+    assert 1e-3 < dt < 5e-2
+    # refining the grid lowers the limit
+    cfg2 = G.config_default(a=0.99, nr=128, nth=128, r_in=1.03, r_out=20.0)
+    assert G.cfl_dt(cfg2) < dt
+
+
+def test_invalid_config_is_rejected_without_gpu():
+    cfg = G.config_default(a=1.5)
+    with pytest.raises(G.GrpicError):
+        G.Context(cfg)

@@ -66,6 +66,28 @@ def test_metric_derivatives_match_finite_differences(a):
             assert abs(d[2 * n + 1] - ft) < 1e-8 * sc
 
 
+@pytest.mark.parametrize("k", [0, 1])
+def test_metric_divided_differences(k):
+    """The cancellation-free divided differences used by the discrete-gradient
+    scheme equal the plain quotient of the metric for a finite step and the
+    analytic derivative at the midpoint for a tiny one."""
+    idx = [0, 1, 6, 7, 8, 9]
+    for a in (0.0, 0.9, 0.99):
+        for r, th in zip(*_rand_points(8, a)):
+            dx = 0.05
+            r1, t1 = (r + dx, th) if k == 0 else (r, th + dx)
+            m0, m1 = O.metric(a, r, th), O.metric(a, r1, t1)
+            plain = np.array([(m1[i] - m0[i]) / dx for i in idx])
+            dd = O.metric_divdiff(a, k, r, th, r1, t1)
+            assert np.allclose(dd, plain, rtol=1e-11, atol=1e-13)
+            dx = 1e-8
+            r1, t1 = (r + dx, th) if k == 0 else (r, th + dx)
+            d = O.metric_deriv(a, r + (dx / 2 if k == 0 else 0), th + (dx / 2 if k == 1 else 0))
+            dd = O.metric_divdiff(a, k, r, th, r1, t1)
+            assert np.allclose(dd, d[[k, 2 + k, 4 + k, 6 + k, 8 + k, 10 + k]], rtol=1e-12,
+                               atol=1e-14)
+
+
 # --------------------------------------------------------- equations of motion
 def _grad(fun, z, h=1e-6):
     g = np.zeros(6)
