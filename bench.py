@@ -65,7 +65,7 @@ WORKLOADS = {
 }
 
 
-def make_context(G, W, n=None):
+def make_context(G, W, n=None, push_wps=0):
     a = W["a"]
     rp = rplus(a)
     evolve = W["mode"] == "evolve"
@@ -76,7 +76,8 @@ def make_context(G, W, n=None):
         pusher=G.PUSH_HYB2, hyb_threshold=W["thr"], max_particles=n,
         r_remove_in=rp, r_remove_out=W["r_out"], reflect=1,
         r_abs=W.get("r_abs", 0.0), chi0=1e4 if evolve else 0.0, lambda_abs=5.0,
-        guess=G.GUESS_RK4)
+        guess=G.GUESS_RK4, sort_every=W.get("sort_every", 50),
+        push_waves_per_simd=push_wps)
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
     ctx = G.Context(cfg)
     ctx.set_fields_wald(1.0)
@@ -151,6 +152,24 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
             "t_particle_s": t_part, "t_grid_s": t_grid}
 
 
+def copy_calibration(nbytes):
+    """One device-to-device copy of nbytes with the HIP runtime's own blit
+    kernel: a kernel of known traffic for scaling the FETCH_SIZE / WRITE_SIZE
+    counters."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    a, b = C.c_void_p(), C.c_void_p()
+    assert hip.hipMalloc(C.byref(a), C.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(C.byref(b), C.c_size_t(nbytes)) == 0
+    assert hip.hipMemset(a, 1, C.c_size_t(nbytes)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3) == 0  # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"copy_calibration_bytes": nbytes}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,10 +178,16 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--particles", type=int, default=0, help="override particle count")
     ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
+    ap.add_argument("--push-wps", type=int, default=0, help="explicit-push waves per SIMD")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many bytes (counter scale)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the path "
               "is built and measured on a single MI355X", file=sys.stderr)
@@ -172,7 +197,7 @@ def main():
     W = dict(WORKLOADS[args.workload])
     if args.particles:
         W["n"] = args.particles
-    ctx, cfg = make_context(G, W)
+    ctx, cfg = make_context(G, W, push_wps=args.push_wps)
     print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,
           flush=True)
     ctx.use_graph(bool(args.graph))
@@ -237,10 +262,12 @@ def main():
         "config": {"workload": W["desc"], "particles": W["n"], "grid": [W["nr"], W["nth"]],
                    "dt": cfg.dt, "pusher": "Hyb2 (RK4 -> IMR)", "threshold": cfg.hyb_threshold,
                    "guess": "RK4 result", "fields": "FP32", "particle_state": "FP64",
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "sort_every": cfg.sort_every,
+                   "tile": [cfg.tile_r, cfg.tile_th]},
         "implicit_fraction": impl / max(args.steps * n_alive, 1),
         "mean_implicit_iterations": float(iters / max(impl, 1)),
         "h_error": herr_percentiles(d1["herr_hist"]),
+        "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -117,6 +117,9 @@ typedef struct grpic_config {
   int tile_r, tile_th;   /* tile size in cells for sorting / deposit bins  */
   int block;             /* threads per block for particle kernels (0 = 256)*/
   int persistent_waves;  /* waves per CU of the implicit-queue kernel (0=8) */
+  int push_waves_per_simd; /* register budget of the explicit push: 0 = the
+                              compiler's choice, 4 = at most 128 VGPRs so that
+                              4 waves fit per SIMD (set by grpic_autotune)  */
 } grpic_config;
 
 /* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */
@@ -219,6 +222,8 @@ typedef struct grpic_diag {
   long herr_hist[GRPIC_HIST_BINS]; /* log10 energy-violation bins of the
                                       last step: bin b holds values in
                                       [10^(b/2-30), 10^((b+1)/2-30))       */
+  long deposit_fallback; /* deposit blocks whose node box did not fit the
+                            on-chip bins (cumulative)                      */
 } grpic_diag;
 int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
 /* Grid diagnostics on the integer chain: max |Gauss residual| over interior

@@ -13,7 +13,7 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgrpic.so")
+LIB_PATH = os.environ.get("GRPIC_LIBRARY") or os.path.join(_HERE, "libgrpic.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "grpic.h")
 _LIB = None
 
@@ -44,7 +44,8 @@ class Config(C.Structure):
                 ("r_remove_in", C.c_double), ("r_remove_out", C.c_double),
                 ("reflect", C.c_int), ("max_particles", C.c_long),
                 ("sort_every", C.c_int), ("tile_r", C.c_int), ("tile_th", C.c_int),
-                ("block", C.c_int), ("persistent_waves", C.c_int)]
+                ("block", C.c_int), ("persistent_waves", C.c_int),
+                ("push_waves_per_simd", C.c_int)]
 
 
 class InitSpec(C.Structure):
@@ -57,7 +58,7 @@ class Diag(C.Structure):
     _fields_ = [("steps", C.c_long), ("alive", C.c_long), ("removed", C.c_long),
                 ("implicit_steps", C.c_long), ("noconv", C.c_long),
                 ("reflected", C.c_long), ("iter_hist", C.c_long * HIST_BINS),
-                ("herr_hist", C.c_long * HIST_BINS)]
+                ("herr_hist", C.c_long * HIST_BINS), ("deposit_fallback", C.c_long)]
 
 
 def lib():
@@ -235,7 +236,8 @@ class Context:
         return {"steps": d.steps, "alive": d.alive, "removed": d.removed,
                 "implicit_steps": d.implicit_steps, "noconv": d.noconv,
                 "reflected": d.reflected, "iter_hist": np.array(d.iter_hist[:]),
-                "herr_hist": np.array(d.herr_hist[:])}
+                "herr_hist": np.array(d.herr_hist[:]),
+                "deposit_fallback": d.deposit_fallback}
 
     def field_diagnostics(self):
         g, b = C.c_double(), C.c_double()

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 
 #include "kerr_device.hpp"
@@ -105,6 +106,8 @@ void validate(const grpic_config& c) {
     if (!(c.r_in > 0.0 && c.r_out > c.r_in)) bad("need 0 < r_in < r_out");
     if (!(c.theta0 > 0.0 && c.theta0 < 0.5 * kPi)) bad("theta0 must lie in (0, pi/2)");
     if (c.tile_r < 1 || c.tile_th < 1) bad("tile sizes must be positive");
+    if ((long)((c.nr + c.tile_r - 1) / c.tile_r) * ((c.nth + c.tile_th - 1) / c.tile_th) > 16384)
+      bad("too many sort tiles (at most 16384): enlarge tile_r / tile_th");
     if (c.dt < 0.0) bad("dt must be positive with a grid");
   }
 }
@@ -137,10 +140,16 @@ void alloc_particles(grpic_ctx* c, long cap) {
   P.r_old = evolve ? dalloc<double>(n) : nullptr;
   P.th_old = evolve ? dalloc<double>(n) : nullptr;
   P.dphi = evolve ? dalloc<double>(n) : nullptr;
+  c->xqueue = evolve ? dalloc<int>(n) : nullptr;
   if (c->cfg.pusher != GRPIC_PUSH_RK4) {
-    c->queue = dalloc<int>(n);
+    // explicit-pass block b appends to segment b % kQueueSegs, so a segment
+    // holds at most ceil(blocks / kQueueSegs) blocks of 256 entries
+    long blocks = (n + 255) / 256;
+    c->seg_cap = (unsigned)(((blocks + kQueueSegs - 1) / kQueueSegs) * 256);
+    size_t qlen = (size_t)c->seg_cap * kQueueSegs;
+    c->queue = dalloc<int>(qlen);
     if (c->cfg.guess != GRPIC_GUESS_PLAIN)
-      for (int i = 0; i < 6; ++i) c->gz[i] = dalloc<double>(n);
+      for (int i = 0; i < 6; ++i) c->gz[i] = dalloc<double>(qlen);
   }
   c->cap = cap;
 }
@@ -171,6 +180,7 @@ void free_particles(grpic_ctx* c) {
     dfree(V->dphi);
   }
   dfree(c->queue);
+  dfree(c->xqueue);
   for (int i = 0; i < 6; ++i) dfree(c->gz[i]);
 }
 
@@ -205,6 +215,13 @@ void setup_grid(grpic_ctx* c) {
   c->idrh = dalloc<double>(idrh.size());
   c->tab.inv_drn = dalloc<float>(g.nr);
   c->tab.inv_drd = dalloc<float>(g.nr + 1);
+  std::vector<double> st(g.nth + 1), ct(g.nth + 1);
+  for (int j = 0; j <= g.nth; ++j) {
+    st[j] = sin(c->h_tn[j]);
+    ct[j] = cos(c->h_tn[j]);
+  }
+  c->stn = dalloc<double>(g.nth + 1);
+  c->ctn = dalloc<double>(g.nth + 1);
   auto up = [&](void* d, const void* h, size_t b) {
     GRPIC_HIP(hipMemcpy(d, h, b, hipMemcpyHostToDevice));
   };
@@ -216,6 +233,8 @@ void setup_grid(grpic_ctx* c) {
   up(c->idrh, idrh.data(), sizeof(double) * idrh.size());
   up(c->tab.inv_drn, fdrn.data(), sizeof(float) * g.nr);
   up(c->tab.inv_drd, fdrd.data(), sizeof(float) * (g.nr + 1));
+  up(c->stn, st.data(), sizeof(double) * (g.nth + 1));
+  up(c->ctn, ct.data(), sizeof(double) * (g.nth + 1));
 }
 #pragma clang fp contract(on)
 
@@ -272,6 +291,8 @@ void free_all(grpic_ctx* c) {
   dfree(c->th);
   dfree(c->idrn);
   dfree(c->idrh);
+  dfree(c->stn);
+  dfree(c->ctn);
   for (int t = 0; t < 4; ++t) {
     dfree(c->tab.krr[t]);
     dfree(c->tab.ktt[t]);
@@ -526,7 +547,7 @@ int grpic_config_default(grpic_config* cfg) {
   cfg->max_particles = 0;
   cfg->sort_every = 0;
   cfg->tile_r = 32;
-  cfg->tile_th = 32;
+  cfg->tile_th = 16;
   cfg->block = 256;
   cfg->persistent_waves = 8;
   return GRPIC_OK;
@@ -711,6 +732,7 @@ int grpic_init_particles(grpic_ctx* c, const grpic_init_spec* s) {
     GRPIC_HIP(hipStreamSynchronize(c->stream));
     dfree(dmj);
     c->qw_max = fabs(s->w);
+    c->has_neutral = s->kind == GRPIC_INIT_ORBITS;
     particles_loaded(c);
     GRPIC_HIP(hipStreamSynchronize(c->stream));
   });
@@ -746,12 +768,14 @@ int grpic_load_particles(grpic_ctx* c, long n, const double* r,
       std::vector<uint8_t> fl(n, GRPIC_FLAG_ALIVE), it(n, 0);
       std::vector<uint32_t> id(n);
       double qwm = 0.0;
+      c->has_neutral = false;
       for (long k = 0; k < n; ++k) {
         if (!(qm[k] == 1.0 || qm[k] == -1.0 || qm[k] == 0.0))
           throw Error(GRPIC_E_INVALID, "q/m must be +1, -1 or 0");
         q[k] = (int8_t)qm[k];
         id[k] = (uint32_t)k;
         if (q[k] != 0) qwm = std::max(qwm, fabs(w[k]));
+        else c->has_neutral = true;
       }
       up(P.qm, q.data(), n);
       up(P.flags, fl.data(), n);
@@ -846,20 +870,24 @@ int grpic_get_diagnostics(grpic_ctx* c, grpic_diag* out) {
   return guarded(c, [&] {
     check_ctx(c);
     if (!out) throw Error(GRPIC_E_INVALID, "null pointer");
-    Stats s;
+    std::unique_ptr<Stats> sp(new Stats);
+    const Stats& s = *sp;
     GRPIC_HIP(hipStreamSynchronize(c->stream));
-    GRPIC_HIP(hipMemcpy(&s, c->stats, sizeof(Stats), hipMemcpyDeviceToHost));
+    GRPIC_HIP(hipMemcpy(sp.get(), c->stats, sizeof(Stats), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     out->steps = c->steps;
-    out->alive = (long)s.alive;
-    out->removed = (long)s.removed;
-    out->implicit_steps = (long)s.implicit_steps;
-    out->noconv = (long)s.noconv;
-    out->reflected = (long)s.reflected;
-    for (int i = 0; i < GRPIC_HIST_BINS; ++i) {
-      out->iter_hist[i] = (long)s.iter_hist[i];
-      out->herr_hist[i] = (long)s.herr_hist[i];
+    for (const StatRep& r : s.rep) {
+      out->alive += (long)r.alive;
+      out->removed += (long)r.removed;
+      out->implicit_steps += (long)r.implicit_steps;
+      out->noconv += (long)r.noconv;
+      out->reflected += (long)r.reflected;
+      for (int i = 0; i < GRPIC_HIST_BINS; ++i) {
+        out->iter_hist[i] += (long)r.iter_hist[i];
+        out->herr_hist[i] += (long)r.herr_hist[i];
+      }
     }
+    out->deposit_fallback = (long)s.deposit_fallback;
   });
 }
 

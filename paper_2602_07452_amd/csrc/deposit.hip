@@ -11,6 +11,8 @@
 // particles are processed.  A finalize pass turns the sums into densitized
 // FP32 sqrt(g) rho, sqrt(g) J^r, sqrt(g) J^theta, sqrt(g) J^phi and clears
 // the accumulators.
+#include <algorithm>
+
 #include "deposit_device.hpp"
 
 namespace grpic {
@@ -20,18 +22,48 @@ struct DepArgs {
   ParticleView p;
   DepositAcc acc;
   int nr, nth;
+  unsigned* fallback;  // blocks that used global atomics (diagnostic)
+  int* xqueue;         // particles whose move crosses a node-cell boundary
+  unsigned* xcount;
 };
 
-__device__ __forceinline__ void acc_add(long long* a, long idx, double v,
-                                        double scale) {
+// Where contributions go: the global accumulators, or a block's LDS bins
+// covering node columns [p0, p0 + bw) and rows [q0, q0 + bh).  The four
+// arrays use the node indexing of their own sub-grid (Fr: r-half column i
+// for i + 1/2, Ft: theta-half row j for j + 1/2).
+struct GlobalSink {
+  const DepositAcc* acc;
+  int nr;
+  __device__ __forceinline__ long long* slot(int a, int i, int j) const {
+    switch (a) {
+      case 0: return acc->Q + (long)j * (nr + 1) + i;
+      case 1: return acc->P + (long)j * (nr + 1) + i;
+      case 2: return acc->Fr + (long)j * nr + i;
+      default: return acc->Ft + (long)j * (nr + 1) + i;
+    }
+  }
+};
+
+struct LdsSink {
+  long long* bins;  // 4 arrays of bw * bh
+  int p0, q0, bw, n;
+  __device__ __forceinline__ long long* slot(int a, int i, int j) const {
+    return bins + a * n + (j - q0) * bw + (i - p0);
+  }
+};
+
+template <class Sink>
+__device__ __forceinline__ void sink_add(const Sink& S, int a, int i, int j,
+                                         double v, double scale) {
   long long q = llrint(v * scale);
   if (q != 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(a + idx),
+    atomicAdd(reinterpret_cast<unsigned long long*>(S.slot(a, i, j)),
               static_cast<unsigned long long>(q));
 }
 
 // face fluxes (in charge units) of a weight change inside node cell (p, q)
-__device__ __forceinline__ void cell_flux(const DepArgs& A, int p, int q,
+template <class Sink>
+__device__ __forceinline__ void cell_flux(const Sink& S, double s, int p, int q,
                                           const double* W0, const double* W1,
                                           double qw) {
   double dSr = (W1[1] + W1[3]) - (W0[1] + W0[3]);
@@ -41,23 +73,73 @@ __device__ __forceinline__ void cell_flux(const DepArgs& A, int p, int q,
   double Fr0 = dSr - Fr1;
   double Ft1 = dW11 - Fr1;
   double Ft0 = dSt - Ft1;
-  double s = A.acc.scale;
-  acc_add(A.acc.Fr, (long)q * A.nr + p, qw * Fr0, s);
-  acc_add(A.acc.Fr, (long)(q + 1) * A.nr + p, qw * Fr1, s);
-  acc_add(A.acc.Ft, (long)q * (A.nr + 1) + p, qw * Ft0, s);
-  acc_add(A.acc.Ft, (long)q * (A.nr + 1) + p + 1, qw * Ft1, s);
+  sink_add(S, 2, p, q, qw * Fr0, s);
+  sink_add(S, 2, p, q + 1, qw * Fr1, s);
+  sink_add(S, 3, p, q, qw * Ft0, s);
+  sink_add(S, 3, p + 1, q, qw * Ft1, s);
 }
 
-__global__ __launch_bounds__(256) void k_deposit(DepArgs A) {
+// what the deposit reads of one particle, loaded in one burst so that the
+// next particle's loads are in flight while this one is accumulated
+struct PRec {
+  double Wo[4], Wn[4], dphi, qw;
+  int c0, c1;
+  bool act;
+};
+
+__device__ __forceinline__ void load_rec(const ParticleView& P, long k, long end,
+                                         PRec& d) {
+  d.act = false;
+  if (k >= end) return;
+  uint8_t fl = P.flags[k];
+  int8_t qm = P.qm[k];
+  double w = P.w[k];
+  d.c0 = P.cell[k];
+  d.c1 = P.celln[k];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    d.Wo[c] = P.W[c][k];
+    d.Wn[c] = P.Wn[c][k];
+  }
+  d.dphi = P.dphi[k];
+  d.qw = (double)qm * w;
+  d.act = (fl & GRPIC_FLAG_ALIVE) && d.qw != 0.0;
+}
+
+// charge and J^phi of a particle, and its face fluxes when the move stays in
+// one node cell (returns false for a crossing move: fluxes left to
+// deposit_crossing)
+template <class Sink>
+__device__ bool deposit_particle(const DepArgs& A, const Sink& S, const PRec& d) {
+  const double s = A.acc.scale;
+  const double qw = d.qw;
+  const int p0 = d.c0 % A.nr, q0 = d.c0 / A.nr, p1 = d.c1 % A.nr, q1 = d.c1 / A.nr;
+  const double hdphi = 0.5 * qw * d.dphi;
+  const bool same = d.c0 == d.c1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int di = c & 1, dj = c >> 1;
+    sink_add(S, 0, p1 + di, q1 + dj, qw * d.Wn[c], s);
+    if (same) {  // old and new J^phi shares land on the same nodes
+      sink_add(S, 1, p1 + di, q1 + dj, hdphi * (d.Wo[c] + d.Wn[c]), s);
+    } else {
+      sink_add(S, 1, p0 + di, q0 + dj, hdphi * d.Wo[c], s);
+      sink_add(S, 1, p1 + di, q1 + dj, hdphi * d.Wn[c], s);
+    }
+  }
+  if (same) {
+    cell_flux(S, s, p0, q0, d.Wo, d.Wn, qw);
+    return true;
+  }
+  return false;
+}
+
+// face fluxes of a move that crosses node-cell boundaries: the straight move
+// is walked cell by cell
+template <class Sink>
+__device__ void deposit_crossing(const DepArgs& A, const Sink& S, long k,
+                                 double qw, int p0, int q0, int p1, int q1) {
   const ParticleView& P = A.p;
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
-  if (!(P.flags[k] & GRPIC_FLAG_ALIVE)) return;
-  const int nrn = A.nr + 1;
-  double qw = (double)P.qm[k] * P.w[k];
-  if (qw == 0.0) return;
-  int c0 = P.cell[k], c1 = P.celln[k];
-  int p0 = c0 % A.nr, q0 = c0 / A.nr, p1 = c1 % A.nr, q1 = c1 / A.nr;
   double Wo[4], Wn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -65,21 +147,6 @@ __global__ __launch_bounds__(256) void k_deposit(DepArgs A) {
     Wn[c] = P.Wn[c][k];
   }
   const double s = A.acc.scale;
-  const double hdphi = 0.5 * qw * P.dphi[k];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    int di = c & 1, dj = c >> 1;
-    long nn = (long)(q1 + dj) * nrn + p1 + di;
-    long no = (long)(q0 + dj) * nrn + p0 + di;
-    acc_add(A.acc.Q, nn, qw * Wn[c], s);
-    acc_add(A.acc.P, no, hdphi * Wo[c], s);
-    acc_add(A.acc.P, nn, hdphi * Wn[c], s);
-  }
-  if (c0 == c1) {
-    cell_flux(A, p0, q0, Wo, Wn, qw);
-    return;
-  }
-  // walk the move through the node cells it crosses
   const double r0 = P.r_old[k], t0 = P.th_old[k], r1 = P.r[k], t1 = P.th[k];
   int cp = p0, cq = q0;
   double Wa[4] = {Wo[0], Wo[1], Wo[2], Wo[3]};
@@ -92,39 +159,191 @@ __global__ __launch_bounds__(256) void k_deposit(DepArgs A) {
     else if (q1 < cq) bt = cq;
     if (br >= 0) tr = (A.g.rn[br] - r0) / (r1 - r0);
     if (bt >= 0) tt = (A.g.tn[bt] - t0) / (t1 - t0);
-    double xr, xt, Wb[4], Wc[4], jump;
+    double xr, xt, Wb[4], Wc[4];
     if (tr <= tt) {
       xr = A.g.rn[br];
       xt = t0 + tr * (t1 - t0);
       dep_weights(A.g, xr, xt, cp, cq, Wb);
-      cell_flux(A, cp, cq, Wa, Wb, qw);
+      cell_flux(S, s, cp, cq, Wa, Wb, qw);
       int np = (br > cp) ? cp + 1 : cp - 1;
       dep_weights(A.g, xr, xt, np, cq, Wc);
       // node (br, cq+1): slot 3 of the old cell if br = cp+1 else slot 2;
       // in the new cell slot 2 if br = np else slot 3
       double prev = (br == cp + 1) ? Wb[3] : Wb[2];
       double now = (br == np) ? Wc[2] : Wc[3];
-      jump = now - prev;
-      acc_add(A.acc.Ft, (long)cq * nrn + br, qw * jump, s);
+      sink_add(S, 3, br, cq, qw * (now - prev), s);
       cp = np;
     } else {
       xr = r0 + tt * (r1 - r0);
       xt = A.g.tn[bt];
       dep_weights(A.g, xr, xt, cp, cq, Wb);
-      cell_flux(A, cp, cq, Wa, Wb, qw);
+      cell_flux(S, s, cp, cq, Wa, Wb, qw);
       int nq = (bt > cq) ? cq + 1 : cq - 1;
       dep_weights(A.g, xr, xt, cp, nq, Wc);
       // node (cp+1, bt): slot 3 of the old cell if bt = cq+1 else slot 1
       double prev = (bt == cq + 1) ? Wb[3] : Wb[1];
       double now = (bt == nq) ? Wc[1] : Wc[3];
-      jump = now - prev;
-      acc_add(A.acc.Fr, (long)bt * A.nr + cp, qw * jump, s);
+      sink_add(S, 2, cp, bt, qw * (now - prev), s);
       cq = nq;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) Wa[c] = Wc[c];
   }
-  cell_flux(A, cp, cq, Wa, Wn, qw);
+  cell_flux(S, s, cp, cq, Wa, Wn, qw);
+}
+
+constexpr int kDepBlock = 512;
+constexpr int kDepChunk = 8192;   // particles per block
+constexpr int kDepSub = 2048;     // segment length when the chunk box is too big
+constexpr int kDepBins = 2048;    // LDS nodes per array (4 arrays x 16 KB)
+
+// Bounding box (node-cell columns box[0..1], rows box[2..3]) of the old and
+// new cells of the charged particles in [beg, end); block-uniform result.
+__device__ __forceinline__ void segment_box(const DepArgs& A, long beg, long end,
+                                            int* box) {
+  const ParticleView& P = A.p;
+  __syncthreads();  // previous users of box / bins are done
+  if (threadIdx.x == 0) {
+    box[0] = 1 << 30;
+    box[1] = -1;
+    box[2] = 1 << 30;
+    box[3] = -1;
+  }
+  __syncthreads();
+  int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
+  for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
+    if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) continue;
+    int c0 = P.cell[k], c1 = P.celln[k];
+    int p0 = c0 % A.nr, q0 = c0 / A.nr, p1 = c1 % A.nr, q1 = c1 / A.nr;
+    pmin = min(pmin, min(p0, p1));
+    pmax = max(pmax, max(p0, p1));
+    qmin = min(qmin, min(q0, q1));
+    qmax = max(qmax, max(q0, q1));
+  }
+  if (pmax >= 0) {
+    atomicMin(&box[0], pmin);
+    atomicMax(&box[1], pmax);
+    atomicMin(&box[2], qmin);
+    atomicMax(&box[3], qmax);
+  }
+  __syncthreads();
+}
+
+// Crossing moves are collected per wave in LDS (kXList entries) and
+// appended to the global crossing queue with one atomic per flush.
+constexpr int kXList = 256;
+
+struct WaveList {
+  int* e;  // this wave's LDS list
+  int n;   // entries held (uniform across the wave)
+};
+
+__device__ __forceinline__ void flush_list(const DepArgs& A, WaveList& X) {
+  if (X.n == 0) return;
+  const int lane = threadIdx.x & 63;
+  __threadfence_block();  // the wave's LDS appends are visible to all lanes
+  unsigned base = 0;
+  if (lane == 0) base = atomicAdd(A.xcount, (unsigned)X.n);
+  base = __shfl(base, 0, 64);
+  for (int i = lane; i < X.n; i += 64) A.xqueue[base + i] = X.e[i];
+  __threadfence_block();  // reads done before the list is refilled
+  X.n = 0;
+}
+
+__device__ __forceinline__ void deposit_range(const DepArgs& A, long beg,
+                                              long end, const LdsSink* L,
+                                              WaveList& X) {
+  const ParticleView& P = A.p;
+  GlobalSink Gs{&A.acc, A.nr};
+  const int lane = threadIdx.x & 63;
+  PRec cur, nxt;
+  load_rec(P, beg + threadIdx.x, end, cur);
+  for (long kb = beg; kb < end; kb += kDepBlock) {  // uniform trip count
+    const long k = kb + threadIdx.x;
+    load_rec(P, k + kDepBlock, end, nxt);  // prefetch the next particle
+    bool cross = false;
+    if (cur.act) {
+      bool done = L ? deposit_particle(A, *L, cur) : deposit_particle(A, Gs, cur);
+      cross = !done;
+    }
+    unsigned long long m = __ballot(cross);
+    if (m) {
+      if (X.n + 64 > kXList) flush_list(A, X);
+      if (cross) X.e[X.n + __popcll(m & ((1ull << lane) - 1ull))] = (int)k;
+      X.n += __popcll(m);
+    }
+    cur = nxt;
+  }
+}
+
+// face fluxes of the queued crossing moves (grid-stride over the queue,
+// global atomics)
+__global__ __launch_bounds__(256) void k_deposit_crossing(DepArgs A) {
+  const ParticleView& P = A.p;
+  GlobalSink Gs{&A.acc, A.nr};
+  const unsigned nq = *A.xcount;
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+       i += gridDim.x * blockDim.x) {
+    long k = A.xqueue[i];
+    int c0 = P.cell[k], c1 = P.celln[k];
+    double qw = (double)P.qm[k] * P.w[k];
+    deposit_crossing(A, Gs, k, qw, c0 % A.nr, c0 / A.nr, c1 % A.nr, c1 / A.nr);
+  }
+}
+
+__global__ void k_reset_xcount(unsigned* x) { *x = 0u; }
+
+// One block deposits a contiguous chunk of (tile-sorted) particles: the node
+// box covering every old and new cell of the chunk is accumulated in LDS and
+// flushed once.  A chunk whose box does not fit is redone in segments of
+// kDepSub particles with their own boxes; a segment that still does not fit
+// uses global atomics.
+__global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
+  __shared__ long long bins[4 * kDepBins];
+  __shared__ int box[4];
+  __shared__ int xlist[(kDepBlock / 64) * kXList];
+  WaveList X{xlist + (threadIdx.x >> 6) * kXList, 0};
+  const long beg = (long)blockIdx.x * kDepChunk;
+  const long end = min(beg + (long)kDepChunk, A.p.n);
+  for (int pass = 0; pass < 2; ++pass) {
+    const long seg = pass == 0 ? kDepChunk : kDepSub;
+    bool redo = false;
+    for (long sb = beg; sb < end; sb += seg) {
+      const long se = min(sb + seg, end);
+      segment_box(A, sb, se, box);
+      if (box[1] < 0) continue;  // nothing charged in this segment
+      const int bp0 = box[0], bq0 = box[2];
+      const int bw = box[1] - bp0 + 2, bh = box[3] - bq0 + 2;
+      const bool fits = bw * bh <= kDepBins;
+      if (!fits && pass == 0) {
+        redo = true;
+        break;
+      }
+      if (!fits) {
+        if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
+        deposit_range(A, sb, se, nullptr, X);
+        continue;
+      }
+      LdsSink L{bins, bp0, bq0, bw, bw * bh};
+      for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
+      __syncthreads();
+      deposit_range(A, sb, se, &L, X);
+      __syncthreads();
+      GlobalSink Gs{&A.acc, A.nr};
+      for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
+        long long v = bins[i];
+        if (v == 0) continue;
+        int a = i / L.n, r = i - a * L.n;
+        int jj = r / bw, ii = r - jj * bw;
+        // r-flux lives on cells (i < nr), theta-flux on rows j < nth
+        if ((a == 2 && bp0 + ii >= A.nr) || (a == 3 && bq0 + jj >= A.nth)) continue;
+        atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
+                  static_cast<unsigned long long>(v));
+      }
+    }
+    if (!redo) break;
+  }
+  flush_list(A, X);
 }
 
 // charge of the current positions only (initial rho)
@@ -139,7 +358,10 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     long nn = (long)(q0 + (c >> 1)) * (A.nr + 1) + p0 + (c & 1);
-    acc_add(A.acc.Q, nn, qw * P.W[c][k], A.acc.scale);
+    long long q = llrint(qw * P.W[c][k] * A.acc.scale);
+    if (q != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(A.acc.Q + nn),
+                static_cast<unsigned long long>(q));
   }
 }
 
@@ -216,8 +438,14 @@ void launch_deposit(grpic_ctx* c) {
     A.acc = c->acc;
     A.nr = c->nr;
     A.nth = c->nth;
-    hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n, 256)), dim3(256), 0,
+    A.fallback = &c->stats->deposit_fallback;
+    A.xqueue = c->xqueue;
+    A.xcount = &c->stats->cross_count;
+    hipLaunchKernelGGL(k_reset_xcount, dim3(1), dim3(1), 0, c->stream, A.xcount);
+    hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n, kDepChunk)), dim3(kDepBlock), 0,
                        c->stream, A);
+    unsigned xb = (unsigned)std::min<long>(grid_for(c->n, 256), 4L * c->num_cus);
+    hipLaunchKernelGGL(k_deposit_crossing, dim3(xb), dim3(256), 0, c->stream, A);
     GRPIC_HIP(hipGetLastError());
   }
   finalize(c, c->jcur ^ 1);  // this step's deposit goes to J[jnext]

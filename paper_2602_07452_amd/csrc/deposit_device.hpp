@@ -12,16 +12,36 @@ namespace grpic {
 // (clamped to the grid)
 __device__ __forceinline__ void node_cell(const GridView& g, double r,
                                           double th, int& p, int& q) {
-  double lr = log(r / g.r_in) * g.inv_dlnr;
+  float lr = radial_coord(g, r);
   double lt = (th - g.th0) * g.inv_dth;
-  p = refine(g.rn, g.nr + 1, r, (int)floor(lr));
+  p = refine(g.rn, g.nr + 1, r, (int)floorf(lr));
   q = refine(g.tn, g.nth + 1, th, (int)floor(lt));
 }
 
-// W[0..3] for nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1)
+// sin and cos of t0 + j h, j = 0..3, from those of t0 and of the small step
+// h (Taylor series to h^9 and h^8, exact to rounding for |h| < 0.05) by the
+// angle-addition recurrence
+__device__ __forceinline__ void sincos_steps(double s0, double c0, double h,
+                                             double* S, double* C) {
+  double h2 = h * h;
+  double sh = h * (1.0 - h2 * (1.0 / 6.0) * (1.0 - h2 * (1.0 / 20.0) *
+                   (1.0 - h2 * (1.0 / 42.0) * (1.0 - h2 * (1.0 / 72.0)))));
+  double ch = 1.0 - h2 * 0.5 * (1.0 - h2 * (1.0 / 12.0) *
+                   (1.0 - h2 * (1.0 / 30.0) * (1.0 - h2 * (1.0 / 56.0))));
+  S[0] = s0;
+  C[0] = c0;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    S[j] = S[j - 1] * ch + C[j - 1] * sh;
+    C[j] = C[j - 1] * ch - S[j - 1] * sh;
+  }
+}
+
+// W[0..3] for nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1); st, ct = sin, cos
+// of th
 __device__ __forceinline__ void dep_weights(const GridView& g, double r,
-                                            double th, int p, int q,
-                                            double* W) {
+                                            double th, double st, double ct,
+                                            int p, int q, double* W) {
   const double a2 = g.a * g.a;
   double ra = g.rn[p], rb = g.rn[p + 1], ta = g.tn[q], tb = g.tn[q + 1];
   double h1r = (r - ra) * (1.0 / 3.0), h2r = (rb - r) * (1.0 / 3.0);
@@ -33,13 +53,20 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
   R[3] = r;
 #pragma unroll
   for (int i = 1; i < 4; ++i) R[3 + i] = r + i * h2r;
+  {
+    double Sa[4], Ca[4], Sb[4], Cb[4];
+    sincos_steps(g.stn[q], g.ctn[q], h1t, Sa, Ca);
+    sincos_steps(st, ct, h2t, Sb, Cb);
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    double t = j < 3 ? ta + j * h1t : (j == 3 ? th : th + (j - 3) * h2t);
-    double s, c;
-    sincos(t, &s, &c);
-    S[j] = fabs(s);
-    C2[j] = a2 * c * c;
+    for (int j = 0; j < 3; ++j) {
+      S[j] = fabs(Sa[j]);
+      C2[j] = a2 * Ca[j] * Ca[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      S[3 + j] = fabs(Sb[j]);
+      C2[3 + j] = a2 * Cb[j] * Cb[j];
+    }
   }
   // trapezoid weights along each half: (1/2, 1, 1, 1/2)
   double Vaa = 0.0, Vba = 0.0, Vab = 0.0, Vbb = 0.0;
@@ -52,26 +79,34 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
     for (int i = 0; i < 7; ++i) {
       double rr = R[i];
       double rho2 = rr * rr + C2[j];
-      double f = S[j] * sqrt(rho2 * (rho2 + 2.0 * rr));
+      double f = fsqrt(rho2 * (rho2 + 2.0 * rr));
       double wa_r = (i == 0 || i == 3) ? 0.5 : (i < 3 ? 1.0 : 0.0);
       double wb_r = (i == 3 || i == 6) ? 0.5 : (i > 3 ? 1.0 : 0.0);
       rowa += wa_r * f;
       rowb += wb_r * f;
     }
-    Vaa += wa_t * rowa;  // [ra, r] x [ta, th]
-    Vba += wa_t * rowb;  // [r, rb] x [ta, th]
-    Vab += wb_t * rowa;  // [ra, r] x [th, tb]
-    Vbb += wb_t * rowb;  // [r, rb] x [th, tb]
+    Vaa += wa_t * S[j] * rowa;  // [ra, r] x [ta, th]
+    Vba += wa_t * S[j] * rowb;  // [r, rb] x [ta, th]
+    Vab += wb_t * S[j] * rowa;  // [ra, r] x [th, tb]
+    Vbb += wb_t * S[j] * rowb;  // [r, rb] x [th, tb]
   }
   Vaa *= h1r * h1t;
   Vba *= h2r * h1t;
   Vab *= h1r * h2t;
   Vbb *= h2r * h2t;
-  double iV = 1.0 / (Vaa + Vba + Vab + Vbb);
+  double iV = frcp(Vaa + Vba + Vab + Vbb);
   W[0] = Vbb * iV;
   W[1] = Vab * iV;
   W[2] = Vba * iV;
   W[3] = Vaa * iV;
+}
+
+__device__ __forceinline__ void dep_weights(const GridView& g, double r,
+                                            double th, int p, int q,
+                                            double* W) {
+  double st, ct;
+  fsincos(th, &st, &ct);
+  dep_weights(g, r, th, st, ct, p, q, W);
 }
 
 }  // namespace grpic

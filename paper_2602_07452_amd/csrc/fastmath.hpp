@@ -1,0 +1,70 @@
+// fastmath.hpp -- FP64 elementary functions for the push, accurate to a few
+// ulp on the argument ranges that occur there and much shorter than the
+// general-purpose library versions (which handle every IEEE corner case).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace grpic {
+
+// 1/x for finite, normal x: hardware estimate refined by two Newton steps
+// (each doubles the number of correct bits).
+__device__ __forceinline__ double frcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// sqrt(x) for finite x > 0 away from the denormal range: hardware estimate
+// of 1/sqrt(x) refined by Goldschmidt's coupled iteration for sqrt(x) and
+// 1/(2 sqrt(x)), with a final residual correction.
+__device__ __forceinline__ double fsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  r = fma(-s, s, x);
+  return fma(h, r, s);
+}
+
+// sin and cos of x for |x| < 100 (polar angles here lie near [0, pi]):
+// Cody-Waite reduction x = k pi/2 + t with pi/2 split in two parts, t in
+// [-pi/4, pi/4]; Taylor polynomials of degree 17 (sin) and 16 (cos), whose
+// truncation error is below 1e-18 on that interval; quadrant from k mod 4.
+__device__ __forceinline__ void fsincos(double x, double* sn, double* cs) {
+  const double two_over_pi = 0.63661977236758134308;
+  const double pio2_hi = 1.5707963267948966;     // pi/2 rounded to double
+  const double pio2_lo = 6.123233995736766e-17;  // pi/2 - pio2_hi
+  double k = rint(x * two_over_pi);
+  double t = fma(-k, pio2_hi, x);
+  t = fma(-k, pio2_lo, t);
+  double t2 = t * t;
+  double ps = -1.0 / 1307674368000.0 + t2 * (1.0 / 355687428096000.0);
+  ps = 1.0 / 6227020800.0 + t2 * ps;
+  ps = -1.0 / 39916800.0 + t2 * ps;
+  ps = 1.0 / 362880.0 + t2 * ps;
+  ps = -1.0 / 5040.0 + t2 * ps;
+  ps = 1.0 / 120.0 + t2 * ps;
+  ps = -1.0 / 6.0 + t2 * ps;
+  ps = fma(t * t2, ps, t);
+  double pc = -1.0 / 87178291200.0 + t2 * (1.0 / 20922789888000.0);
+  pc = 1.0 / 479001600.0 + t2 * pc;
+  pc = -1.0 / 3628800.0 + t2 * pc;
+  pc = 1.0 / 40320.0 + t2 * pc;
+  pc = -1.0 / 720.0 + t2 * pc;
+  pc = 1.0 / 24.0 + t2 * pc;
+  pc = -0.5 + t2 * pc;
+  pc = fma(t2, pc, 1.0);
+  int q = ((int)k) & 3;
+  double s = (q & 1) ? pc : ps;
+  double c = (q & 1) ? ps : pc;
+  *sn = (q & 2) ? -s : s;
+  *cs = ((q + 1) & 2) ? -c : c;
+}
+
+}  // namespace grpic

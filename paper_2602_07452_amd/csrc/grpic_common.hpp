@@ -30,15 +30,27 @@ struct ParticleView {
   double *r_old, *th_old, *dphi;         // previous position, phi change
 };
 
-// device counters written by the particle kernels
-struct Stats {
+// device counters written by the particle kernels.  Counters that many
+// blocks update are replicated (a block uses replica blockIdx % kStatReps)
+// so that no single address takes more than a few thousand atomics a step;
+// the host sums the replicas.
+constexpr int kStatReps = 64;
+constexpr int kQueueSegs = 256;  // the implicit queue is split in segments
+
+struct StatRep {
   unsigned long long implicit_steps, noconv, removed, reflected, alive;
   unsigned long long iter_hist[kHistBins];
   unsigned long long herr_hist[kHistBins];
-  unsigned int queue_count;   // implicit-queue length of the current step
-  unsigned int work_counter;  // persistent-kernel work cursor
-  unsigned int guess_counter; // learned-guess kernel work cursor
-  unsigned int pad;
+  unsigned long long pad[3];
+};
+
+struct Stats {
+  StatRep rep[kStatReps];
+  unsigned int seg_count[kQueueSegs];  // entries in each queue segment
+  unsigned int work_counter;     // persistent-kernel work cursor
+  unsigned int guess_counter;    // learned-guess kernel work cursor
+  unsigned int deposit_fallback; // deposit segments that used global atomics
+  unsigned int cross_count;      // crossing moves queued by the deposit
 };
 
 // fixed-point charge accumulators (int64, deterministic under atomics)
@@ -83,6 +95,7 @@ struct grpic_ctx {
   std::vector<double> h_rn, h_rh, h_tn, h_th;
   double *rn = nullptr, *rh = nullptr, *tn = nullptr, *th = nullptr;
   double *idrn = nullptr, *idrh = nullptr;
+  double *stn = nullptr, *ctn = nullptr;  // sin, cos of the node angles
   grpic::Tables tab{};
   // field levels
   grpic::Level3 D[3]{};  // index: 0 = Dn, 1 = Dh0, 2 = Dh1
@@ -93,10 +106,13 @@ struct grpic_ctx {
   grpic::DepositAcc acc{};
   // particles
   long n = 0, cap = 0;
+  bool has_neutral = false;  // some particle has q/m = 0
   grpic::ParticleView pv{};
   grpic::ParticleView alt{};  // second buffers of the sorted arrays
   double* gz[6]{};       // implicit guesses by queue slot
   int* queue = nullptr;
+  unsigned seg_cap = 0;  // entries per implicit-queue segment
+  int* xqueue = nullptr;  // crossing moves of the deposit
   grpic::Stats* stats = nullptr;
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;

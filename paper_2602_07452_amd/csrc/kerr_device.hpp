@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
 #include "grpic_common.hpp"
 
 namespace grpic {
@@ -28,11 +29,11 @@ struct DMet {  // [0] = d/dr, [1] = d/dtheta
   double da[2], db[2], drr[2], dtt[2], dpp[2], drp[2];
 };
 
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp(double x) { return frcp(x); }
 
 __device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
   double s, c;
-  sincos(th, &s, &c);
+  fsincos(th, &s, &c);
   double a2 = a * a, s2 = s * s;
   double rho2 = r * r + a2 * c * c;
   double S = rho2 + 2.0 * r;
@@ -40,7 +41,7 @@ __device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
   double ixi = rho2 * iS, xi = S * irho2;
   m.s = s;
   m.c = c;
-  m.alpha = sqrt(ixi);
+  m.alpha = fsqrt(ixi);
   m.betar = 2.0 * r * iS;
   m.grr = xi;
   m.gtt = rho2;
@@ -50,20 +51,20 @@ __device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
   m.itt = irho2;
   m.irp = a * irho2;
   m.ipp = irho2 * rcp(s2);
-  m.sg = fabs(s) * sqrt(rho2 * S);
+  m.sg = fabs(s) * fsqrt(rho2 * S);
 }
 
 // metric plus derivatives of alpha, beta^r and gamma^ij
 __device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
                                          DMet& d) {
   double s, c;
-  sincos(th, &s, &c);
+  fsincos(th, &s, &c);
   double a2 = a * a, s2 = s * s, sc = s * c;
   double rho2 = r * r + a2 * c * c;
   double S = rho2 + 2.0 * r;
   double irho2 = rcp(rho2), iS = rcp(S), is2 = rcp(s2);
   double ixi = rho2 * iS, xi = S * irho2;
-  double alpha = sqrt(ixi);
+  double alpha = fsqrt(ixi);
   m.s = s;
   m.c = c;
   m.alpha = alpha;
@@ -76,7 +77,7 @@ __device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
   m.itt = irho2;
   m.irp = a * irho2;
   m.ipp = irho2 * is2;
-  m.sg = fabs(s) * sqrt(rho2 * S);
+  m.sg = fabs(s) * fsqrt(rho2 * S);
   double i4 = irho2 * irho2, ixi2 = ixi * ixi;
   double dr2[2] = {2.0 * r, -2.0 * a2 * sc};
   double dxi[2] = {2.0 * irho2 * (1.0 - 2.0 * r * r * irho2),
@@ -141,7 +142,7 @@ __device__ __forceinline__ double energy(double a, const double* z) {
   double ur = z[3], ut = z[4], up = z[5];
   double q = m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
              2.0 * m.irp * ur * up;
-  return m.alpha * sqrt(1.0 + q) - m.betar * ur;
+  return m.alpha * fsqrt(1.0 + q) - m.betar * ur;
 }
 
 // ---------------------------------------------------------------- gather
@@ -150,7 +151,15 @@ struct GridView {
   double a, r_in, th0, dth, inv_dlnr, inv_dth;
   const double *rn, *rh, *tn, *th;  // coordinates
   const double *idrn, *idrh;        // 1/(rn[i+1]-rn[i]), 1/(rh[i+1]-rh[i])
+  const double *stn, *ctn;          // sin, cos of the node angles
+  float inv_rin_f, l2_dlnr_f;       // 1/r_in, ln(2)/dlnr for the estimate
 };
+
+// radial cell coordinate log(r/r_in)/dlnr to within far less than a cell
+// (FP32 log2); callers refine the index against the FP64 node table
+__device__ __forceinline__ float radial_coord(const GridView& g, double r) {
+  return __log2f((float)r * g.inv_rin_f) * g.l2_dlnr_f;
+}
 
 struct FieldView {  // densitized FP32 components at their Yee points
   const float *Dr, *Dt, *Dp, *Br, *Bt, *Bp;
@@ -172,6 +181,10 @@ inline GridView make_grid_view(const grpic_ctx* c) {
   g.th = c->th;
   g.idrn = c->idrn;
   g.idrh = c->idrh;
+  g.stn = c->stn;
+  g.ctn = c->ctn;
+  g.inv_rin_f = (float)(1.0 / c->cfg.r_in);
+  g.l2_dlnr_f = c->dlnr > 0 ? (float)(0.6931471805599453 / c->dlnr) : 0.0f;
   return g;
 }
 
@@ -195,10 +208,10 @@ struct Stencil {
 
 __device__ __forceinline__ void locate(const GridView& g, double r, double th,
                                        Stencil& S) {
-  double lr = log(r / g.r_in) * g.inv_dlnr;
+  float lr = radial_coord(g, r);
   double lt = (th - g.th0) * g.inv_dth;
-  int pn = refine(g.rn, g.nr + 1, r, (int)floor(lr));
-  int ph = refine(g.rh, g.nr, r, (int)floor(lr - 0.5));
+  int pn = refine(g.rn, g.nr + 1, r, (int)floorf(lr));
+  int ph = refine(g.rh, g.nr, r, (int)floorf(lr - 0.5f));
   int qn = refine(g.tn, g.nth + 1, th, (int)floor(lt));
   int qh = refine(g.th, g.nth, th, (int)floor(lt - 0.5));
   S.pn = pn;
@@ -241,14 +254,16 @@ __device__ __forceinline__ void gather(const GridView& g, const FieldView& F,
 // E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei).
 __device__ __forceinline__ void rhs(double qm, const double* z, const Met& m,
                                     const DMet& d, const double* D,
-                                    const double* B, double* f, double* pw) {
+                                    const double* B, double* f, double* pw,
+                                    double* e = nullptr) {
   double ur = z[3], ut = z[4], up = z[5];
   double Ur = m.irr * ur + m.irp * up;
   double Ut = m.itt * ut;
   double Up = m.irp * ur + m.ipp * up;
-  double G = sqrt(1.0 + ur * Ur + ut * Ut + up * Up);
+  double G = fsqrt(1.0 + ur * Ur + ut * Ut + up * Up);
   double iG = rcp(G);
   double aiG = m.alpha * iG;
+  if (e) *e = m.alpha * G - m.betar * ur;
   f[0] = aiG * Ur - m.betar;
   f[1] = aiG * Ut;
   f[2] = aiG * Up;

@@ -7,9 +7,10 @@
 // inverting a tabulated cumulative distribution), mapped to covariant u_i
 // with the Cholesky factor of gamma_ij (order r, theta, phi).
 //
-// Tile sort: counting sort of the particles by (32 x 32 by default) node-cell
-// tile, dead particles last; keeps a block's particles in a few cells for
-// the gather and the deposit.
+// Tile sort: counting sort of the particles by node-cell tile (32 x 16 cells
+// by default, tiles in serpentine order), dead particles last; keeps a
+// block's particles in a few neighbouring cells for the gather and the
+// deposit.
 #include "deposit_device.hpp"
 
 namespace grpic {
@@ -160,13 +161,27 @@ __device__ __forceinline__ int tile_key(const SortArgs& A, long k) {
   if (!(A.p.flags[k] & GRPIC_FLAG_ALIVE)) return A.ntiles;
   int p, q;
   node_cell(A.g, A.p.r[k], A.p.th[k], p, q);
-  return (q / A.tile_th) * A.ntr + p / A.tile_r;
+  // serpentine order: odd tile rows run backwards in r, so consecutive
+  // tiles are always neighbours
+  int tq = q / A.tile_th, tp = p / A.tile_r;
+  return tq * A.ntr + ((tq & 1) ? A.ntr - 1 - tp : tp);
 }
 
-__global__ void k_tile_count(SortArgs A) {
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= A.p.n) return;
-  atomicAdd(&A.count[tile_key(A, k)], 1);
+constexpr int kSortChunk = 4096;
+
+// per-block histogram of the chunk's tile keys in LDS, one global add per
+// non-empty bin
+__global__ __launch_bounds__(256) void k_tile_count(SortArgs A) {
+  extern __shared__ int hist[];
+  const int nb = A.ntiles + 1;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  long beg = (long)blockIdx.x * kSortChunk, end = min(beg + (long)kSortChunk, A.p.n);
+  for (long k = beg + threadIdx.x; k < end; k += blockDim.x)
+    atomicAdd(&hist[tile_key(A, k)], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if (hist[i]) atomicAdd(&A.count[i], hist[i]);
 }
 
 // exclusive scan of ntiles + 1 counts in one block
@@ -196,28 +211,45 @@ __global__ void k_tile_scan(int* count, int* offset, int n) {
   }
 }
 
-__global__ void k_tile_scatter(SortArgs A) {
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= A.p.n) return;
-  int key = tile_key(A, k);
-  long d = atomicAdd(&A.offset[key], 1);
+// scatter: the block reserves one range per non-empty bin with a single
+// global add, then ranks its particles inside the range with LDS atomics
+__global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
+  extern __shared__ int sh[];
+  const int nb = A.ntiles + 1;
+  int* hist = sh;
+  int* base = sh + nb;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  long beg = (long)blockIdx.x * kSortChunk, end = min(beg + (long)kSortChunk, A.p.n);
+  for (long k = beg + threadIdx.x; k < end; k += blockDim.x)
+    atomicAdd(&hist[tile_key(A, k)], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    base[i] = hist[i] ? atomicAdd(&A.offset[i], hist[i]) : 0;
+    hist[i] = 0;
+  }
+  __syncthreads();
   const ParticleView &S = A.p, &D = A.q;
-  D.r[d] = S.r[k];
-  D.th[d] = S.th[k];
-  D.ph[d] = S.ph[k];
-  D.ur[d] = S.ur[k];
-  D.uth[d] = S.uth[k];
-  D.uph[d] = S.uph[k];
-  D.H0[d] = S.H0[k];
-  D.herr[d] = S.herr[k];
-  D.w[d] = S.w[k];
-  D.qm[d] = S.qm[k];
-  D.flags[d] = S.flags[k];
-  D.iters[d] = S.iters[k];
-  D.id[d] = S.id[k];
+  for (long k = beg + threadIdx.x; k < end; k += blockDim.x) {
+    int key = tile_key(A, k);
+    long d = base[key] + atomicAdd(&hist[key], 1);
+    D.r[d] = S.r[k];
+    D.th[d] = S.th[k];
+    D.ph[d] = S.ph[k];
+    D.ur[d] = S.ur[k];
+    D.uth[d] = S.uth[k];
+    D.uph[d] = S.uph[k];
+    D.H0[d] = S.H0[k];
+    D.herr[d] = S.herr[k];
+    D.w[d] = S.w[k];
+    D.qm[d] = S.qm[k];
+    D.flags[d] = S.flags[k];
+    D.iters[d] = S.iters[k];
+    D.id[d] = S.id[k];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) D.W[c][d] = S.W[c][k];
-  D.cell[d] = S.cell[k];
+    for (int c = 0; c < 4; ++c) D.W[c][d] = S.W[c][k];
+    D.cell[d] = S.cell[k];
+  }
 }
 
 void launch_sort(grpic_ctx* c) {
@@ -235,11 +267,12 @@ void launch_sort(grpic_ctx* c) {
   A.ntiles = c->ntiles;
   A.count = c->tile_count;
   A.offset = c->tile_offset;
-  dim3 g(grid_for(c->n, 256)), b(256);
-  hipLaunchKernelGGL(k_tile_count, g, b, 0, c->stream, A);
+  dim3 g(grid_for(c->n, kSortChunk)), b(256);
+  size_t sh = sizeof(int) * (c->ntiles + 1);
+  hipLaunchKernelGGL(k_tile_count, g, b, sh, c->stream, A);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, c->stream,
                      c->tile_count, c->tile_offset, c->ntiles + 1);
-  hipLaunchKernelGGL(k_tile_scatter, g, b, 0, c->stream, A);
+  hipLaunchKernelGGL(k_tile_scatter, g, b, 2 * sh, c->stream, A);
   GRPIC_HIP(hipGetLastError());
   ParticleView& P = c->pv;
   ParticleView& Q = c->alt;

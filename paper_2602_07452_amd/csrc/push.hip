@@ -7,9 +7,11 @@
 // Two passes per step:
 //  * k_push_explicit: one thread per particle.  RK4 with fields re-gathered
 //    at every stage; the switch either accepts the step or appends the
-//    particle to the implicit queue (wave ballot + one atomic per wave).
-//  * k_push_implicit: persistent kernel; each wave takes 64 queue entries
-//    at a time from a device cursor until the queue is drained.
+//    particle to the implicit queue (wave ballots, one atomic per block on
+//    one of kQueueSegs segment counters).
+//  * k_push_implicit: persistent kernel; each wave takes kGrab entries of
+//    the concatenated segments at a time from a device cursor until the
+//    queue is drained.
 #include "deposit_device.hpp"
 
 namespace grpic {
@@ -29,7 +31,8 @@ struct PushArgs {
   double a, dt, thr, tol, ham_eps, r_min, r_max, th_lo, th_hi;
   int pusher, guess, kmax, reflect;
   double* gz[6];
-  int* queue;
+  int* queue;       // kQueueSegs segments of seg_cap entries
+  unsigned seg_cap;
   Stats* st;
 };
 
@@ -48,7 +51,8 @@ __device__ __forceinline__ void stats_init(LocalStats& s) {
     s.implicit_steps = s.noconv = s.removed = s.reflected = s.alive = 0;
 }
 
-__device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* g) {
+__device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
+  StatRep* g = &st->rep[blockIdx.x % kStatReps];
   for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) {
     if (s.herr_hist[i]) atomicAdd(&g->herr_hist[i], (unsigned long long)s.herr_hist[i]);
     if (s.iter_hist[i]) atomicAdd(&g->iter_hist[i], (unsigned long long)s.iter_hist[i]);
@@ -65,21 +69,24 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* g) {
 // --------------------------------------------------------------- F(z)
 template <bool GRID>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
-                                     const double* z, double* f, double* pw) {
+                                     const double* z, double* f, double* pw,
+                                     double* e = nullptr) {
   Met m;
   DMet d;
   metric_d(A.a, z[0], z[1], m, d);
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
   if (GRID && qm != 0.0) gather(A.g, A.f, z[0], z[1], rcp(m.sg), D, B);
-  rhs(qm, z, m, d, D, B, f, pw);
+  rhs(qm, z, m, d, D, B, f, pw, e);
 }
 
+// RK4; *e0 = energy e at z (from the first stage)
 template <bool GRID>
 __device__ __forceinline__ void rk4(const PushArgs& A, double qm,
-                                    const double* z, double* out, double* Wq) {
+                                    const double* z, double* out, double* Wq,
+                                    double* e0) {
   const double dt = A.dt, hdt = 0.5 * A.dt;
   double k[6], acc[6], y[6], p, pacc;
-  eval<GRID>(A, qm, z, k, &p);
+  eval<GRID>(A, qm, z, k, &p, e0);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] = k[i];
@@ -327,8 +334,9 @@ __device__ __forceinline__ void load_z(const ParticleView& P, long k,
 }
 
 // ------------------------------------------------------- explicit pass
-template <bool GRID, bool EVOLVE>
-__global__ __launch_bounds__(256) void k_push_explicit(PushArgs A) {
+template <bool GRID, bool EVOLVE, int WPS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS)))
+void k_push_explicit(PushArgs A) {
   __shared__ LocalStats ls;
   stats_init(ls);
   __syncthreads();
@@ -346,9 +354,8 @@ __global__ __launch_bounds__(256) void k_push_explicit(PushArgs A) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
     } else {
-      double Wq;
-      rk4<GRID>(A, qm, z, trial, &Wq);
-      double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
+      double Wq, e0;
+      rk4<GRID>(A, qm, z, trial, &Wq, &e0);
       double v = switch_value(A, qm, P.H0[k], e0, trial, Wq);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
@@ -363,43 +370,83 @@ __global__ __launch_bounds__(256) void k_push_explicit(PushArgs A) {
         enq = true;
     }
   }
-  // append the rejected particles to the implicit queue
+  // append the rejected particles to the implicit queue: wave ballots, one
+  // block total, one atomic on the block's queue segment
+  __shared__ unsigned s_off[4], s_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long mask = __ballot(enq);
-  if (mask) {
-    int lane = threadIdx.x & 63;
-    int leader = __ffsll((long long)mask) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(&A.st->queue_count, (unsigned)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (enq) {
-      unsigned slot = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-      A.queue[slot] = (int)k;
-      if (A.guess == GRPIC_GUESS_RK4) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
-      }
+  if (lane == 0) s_off[wave] = (unsigned)__popcll(mask);
+  __syncthreads();
+  const unsigned seg = blockIdx.x % kQueueSegs;
+  if (threadIdx.x == 0) {
+    unsigned tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      unsigned c = s_off[w];
+      s_off[w] = tot;
+      tot += c;
     }
+    s_base = tot ? atomicAdd(&A.st->seg_count[seg], tot) : 0u;
   }
   __syncthreads();
+  if (enq) {
+    unsigned slot = seg * A.seg_cap + s_base + s_off[wave] +
+                    (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    A.queue[slot] = (int)k;
+    if (A.guess == GRPIC_GUESS_RK4) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
+    }
+  }
   stats_flush(ls, A.st);
 }
 
+// exclusive prefix of the queue-segment lengths in LDS (blockDim == kQueueSegs)
+__device__ __forceinline__ unsigned segment_prefix(const Stats* st, unsigned* pref) {
+  const int t = threadIdx.x;
+  pref[t + 1] = st->seg_count[t];
+  if (t == 0) pref[0] = 0;
+  __syncthreads();
+  for (int d = 1; d < kQueueSegs; d <<= 1) {
+    unsigned v = (t + 1 > d) ? pref[t + 1 - d] : 0u;
+    __syncthreads();
+    pref[t + 1] += v;
+    __syncthreads();
+  }
+  return pref[kQueueSegs];
+}
+
+// queue slot of the v-th entry counted across segments
+__device__ __forceinline__ unsigned virtual_slot(const unsigned* pref, unsigned v,
+                                                 unsigned seg_cap) {
+  int lo = 0, hi = kQueueSegs;  // pref[lo] <= v < pref[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pref[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return (unsigned)lo * seg_cap + (v - pref[lo]);
+}
+
 // ------------------------------------------------------- implicit pass
-template <bool GRID, bool EVOLVE>
+constexpr unsigned kGrab = 256;  // queue entries a wave takes at a time
+
+template <bool GRID, bool EVOLVE, bool HAM>
 __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
   __shared__ LocalStats ls;
+  __shared__ unsigned pref[kQueueSegs + 1];
   stats_init(ls);
-  __syncthreads();
+  const unsigned qn = segment_prefix(A.st, pref);
   const ParticleView& P = A.p;
   const int lane = threadIdx.x & 63;
-  const unsigned qn = A.st->queue_count;
   for (;;) {
     unsigned base = 0;
-    if (lane == 0) base = atomicAdd(&A.st->work_counter, 64u);
+    if (lane == 0) base = atomicAdd(&A.st->work_counter, kGrab);
     base = __shfl(base, 0, 64);
     if (base >= qn) break;
-    unsigned slot = base + lane;
-    if (slot < qn) {
+    for (unsigned sub = 0; sub < kGrab; sub += 64) {
+      unsigned v = base + sub + lane;
+      if (v >= qn) break;
+      unsigned slot = virtual_slot(pref, v, A.seg_cap);
       long k = A.queue[slot];
       double z[6], zk[6];
       load_z(P, k, z);
@@ -413,7 +460,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       }
       int it;
       double Wq = 0.0;
-      if (qm == 0.0 && A.pusher != GRPIC_PUSH_IMR)
+      if (HAM && qm == 0.0 && A.pusher != GRPIC_PUSH_IMR)
         it = ham_dg(A, z, zk);
       else
         it = imr<GRID>(A, qm, z, zk, &Wq);
@@ -423,21 +470,25 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         it = -it;
       }
       double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
-      double v = switch_value(A, qm, P.H0[k], e0, zk, Wq);
-      finalize<EVOLVE>(A, k, z, zk, v, it, fl, ls);
+      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq);
+      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls);
     }
   }
   __syncthreads();
   stats_flush(ls, A.st);
 }
 
+// per-step counters back to zero (cumulative counters are kept)
 __global__ void k_reset_step(Stats* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->queue_count = 0;
+  const int t = threadIdx.x;
+  for (int i = t; i < kQueueSegs; i += blockDim.x) st->seg_count[i] = 0;
+  for (int r = 0; r < kStatReps; ++r) {
+    for (int i = t; i < kHistBins; i += blockDim.x) st->rep[r].herr_hist[i] = 0;
+    if (t == 0) st->rep[r].alive = 0;
+  }
+  if (t == 0) {
     st->work_counter = 0;
     st->guess_counter = 0;
-    for (int i = 0; i < kHistBins; ++i) st->herr_hist[i] = 0;
-    st->alive = 0;
   }
 }
 
@@ -467,6 +518,7 @@ static PushArgs make_args(grpic_ctx* c) {
   A.reflect = c->cfg.reflect;
   for (int i = 0; i < 6; ++i) A.gz[i] = c->gz[i];
   A.queue = c->queue;
+  A.seg_cap = c->seg_cap;
   A.st = c->stats;
   return A;
 }
@@ -476,8 +528,12 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   int block = 256;
   hipEvent_t ev;
   time_begin(c, GRPIC_K_PUSH, &ev);
-  hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE>), dim3(grid_for(c->n, block)),
-                     dim3(block), 0, c->stream, A);
+  if (c->cfg.push_waves_per_simd >= 4)
+    hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE, 4>), dim3(grid_for(c->n, block)),
+                       dim3(block), 0, c->stream, A);
+  else
+    hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE, 1>), dim3(grid_for(c->n, block)),
+                       dim3(block), 0, c->stream, A);
   GRPIC_HIP(hipGetLastError());
   time_end(c, GRPIC_K_PUSH, ev);
   bool implicit = c->cfg.pusher != GRPIC_PUSH_RK4;
@@ -489,15 +545,21 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   long need = (c->n + 255) / 256;
   if ((long)blocks > need) blocks = (unsigned)(need < 1 ? 1 : need);
   time_begin(c, GRPIC_K_IMPLICIT, &ev);
-  hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE>), dim3(blocks), dim3(256), 0,
-                     c->stream, A);
+  // the discrete-gradient code is only compiled into the variant used when
+  // neutral particles are present (it needs many more registers)
+  if (c->has_neutral && c->cfg.pusher != GRPIC_PUSH_IMR)
+    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, true>), dim3(blocks), dim3(256), 0,
+                       c->stream, A);
+  else
+    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, false>), dim3(blocks), dim3(256), 0,
+                       c->stream, A);
   GRPIC_HIP(hipGetLastError());
   time_end(c, GRPIC_K_IMPLICIT, ev);
 }
 
 void launch_push(grpic_ctx* c) {
   if (c->n == 0) return;
-  hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(64), 0, c->stream, c->stats);
+  hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(256), 0, c->stream, c->stats);
   GRPIC_HIP(hipGetLastError());
   PushArgs A = make_args(c);
   int mode = c->cfg.field_mode;

@@ -18,7 +18,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_config_default():
     cfg = G.config_default()
-    assert cfg.tol == 1e-13 and cfg.kmax == 50 and cfg.tile_r == 32
+    assert cfg.tol == 1e-13 and cfg.kmax == 50 and cfg.tile_r == 32 and cfg.tile_th == 16
     assert abs(cfg.theta0 - 3.141592653589793 / 200) < 1e-15
 
 
