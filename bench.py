@@ -44,6 +44,51 @@ BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 32 + 4
 BYTES_DEPOSIT = 32 + 32 + 4 + 4 + 1 + 8 + 8 + 1
 
 
+# Kernel per timing group, as named in rocprofv3 traces, and the source files
+# that determine its code: a committed counter summary is only used while its
+# recorded hash of these files still matches.
+GROUP_KERNEL = {"push": "k_push_explicit", "implicit": "k_push_implicit",
+                "deposit": "k_deposit", "fields": "k_ampere", "sort": "k_tile_scatter"}
+GROUP_SOURCES = {"push": "push.hip", "implicit": "push.hip", "deposit": "deposit.hip",
+                 "fields": "maxwell.hip", "sort": "particles.hip"}
+
+
+def kernel_source_hash(group):
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2602_07452_amd", "csrc")
+    files = [GROUP_SOURCES[group]] + sorted(f for f in os.listdir(src) if f.endswith(".hpp"))
+    for f in files:
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "grpic.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(group, workload, particles):
+    """HBM bytes per launch of a timing group's kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary (each counter scaled by its copy-kernel
+    calibration factor); None when there is no summary for this workload or
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{group}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash(group):
+        return None
+    if int(kv.get("particles", -1)) != particles:
+        return None
+    fetch = float(kv["fetch_kib_per_launch"]) * 1024 * float(kv["fetch_factor"])
+    write = float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_factor"])
+    return fetch + write
+
+
 def rplus(a):
     return 1.0 + np.sqrt(1.0 - a * a)
 
@@ -180,7 +225,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
     ap.add_argument("--push-wps", type=int, default=0, help="explicit-push waves per SIMD")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scale)")
@@ -237,14 +282,17 @@ def main():
             achieved = flops[dom] / cnt / avg_s / 1e12
             roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                    "frac": achieved / PEAK_FP64_TFLOPS,
+                    "traffic": counter_traffic(dom, args.workload, W["n"]),
                     "avg_launch_ms": avg_s * 1e3}
         else:
             nbytes = BYTES_DEPOSIT * n_alive if dom == "deposit" else 0
             achieved = nbytes / avg_s / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                    "traffic": counter_traffic(dom, args.workload, W["n"]),
                     "avg_launch_ms": avg_s * 1e3}
+        roof["algorithmic_bytes"] = BYTES_PUSH * n_alive if dom == "push" else None
         roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
                                       if v[1] > 0}
 

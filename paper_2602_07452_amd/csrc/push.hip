@@ -428,7 +428,7 @@ __device__ __forceinline__ unsigned virtual_slot(const unsigned* pref, unsigned 
 }
 
 // ------------------------------------------------------- implicit pass
-constexpr unsigned kGrab = 256;  // queue entries a wave takes at a time
+constexpr unsigned kGrab = 64;  // queue entries a wave takes at a time
 
 template <bool GRID, bool EVOLVE, bool HAM>
 __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
