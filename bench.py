@@ -197,6 +197,66 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
             "t_particle_s": t_part, "t_grid_s": t_grid}
 
 
+def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
+    """The charged test-particle workload (Kerr a=0.9, Wald field on 512^2,
+    2^20 particles) with the implicit midpoint pusher on every particle,
+    started from z^n (plain) and from the learned guess.  The network is
+    trained on the GPU on the converged steps of collect_steps steps of the
+    same workload (other seed).  Both runs converge to the same states, so
+    their H errors agree; the rate counts particle-steps per second."""
+    a = 0.9
+    rp = rplus(a)
+
+    def cfg(guess):
+        return G.config_default(a=a, nr=512, nth=512, r_in=0.9 * rp, r_out=50.0, dt=dt,
+                                field_mode=G.FIELDS_STATIC, pusher=G.PUSH_IMR,
+                                max_particles=n, r_remove_in=rp, r_remove_out=50.0,
+                                reflect=1, guess=guess)
+
+    def init(ctx, c, seed):
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_ISO, n, seed, 2.0, 30.0, c.theta0,
+                           np.pi - c.theta0, 1.0)
+
+    c = cfg(G.GUESS_MLP)
+    with G.Context(c) as ctx:
+        init(ctx, c, SEED + 2)
+        ctx.mlp_collect(collect_steps * n)
+        ctx.step(collect_steps)
+        ctx.mlp_collect(0)
+        samples = ctx.mlp_num_samples()
+        t0 = time.perf_counter()
+        loss = ctx.mlp_train(epochs=epochs, batch=4096, lr=3e-3, lr_final=3e-5, seed=7)
+        t_train = time.perf_counter() - t0
+        net = ctx.mlp_get()
+    out = {"workload": ("charged test particles, Kerr a=0.9, Wald B0=1 on 512x512, "
+                        f"2^20 particles, implicit midpoint on every particle, dt={dt}"),
+           "train": {"samples": samples, "epochs": epochs, "batch": 4096,
+                     "loss_first_epoch": float(loss[0]), "loss_last_epoch": float(loss[-1]),
+                     "seconds": t_train}}
+    for name, guess in (("plain", G.GUESS_PLAIN), ("learned", G.GUESS_MLP)):
+        c = cfg(guess)
+        with G.Context(c) as ctx:
+            init(ctx, c, SEED + 9)
+            if guess == G.GUESS_MLP:
+                ctx.mlp_set(*net)
+            ctx.step(2)
+            ctx.sync()
+            d0 = ctx.diagnostics()
+            t0 = time.perf_counter()
+            ctx.step(steps)
+            ctx.sync()
+            t1 = time.perf_counter()
+            d1 = ctx.diagnostics()
+        h = d1["iter_hist"] - d0["iter_hist"]
+        out[name] = {"value": n * steps / (t1 - t0), "unit": "particle-steps/s",
+                     "mean_iterations": float(h @ np.arange(len(h)) / max(h.sum(), 1)),
+                     "h_error": herr_percentiles(d1["herr_hist"]),
+                     "not_converged": int(d1["noconv"] - d0["noconv"])}
+    out["speedup"] = out["learned"]["value"] / out["plain"]["value"]
+    return out
+
+
 def copy_calibration(nbytes):
     """One device-to-device copy of nbytes with the HIP runtime's own blit
     kernel: a kernel of known traffic for scaling the FETCH_SIZE / WRITE_SIZE
@@ -227,6 +287,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain guess comparison")
+    ap.add_argument("--learned-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scale)")
     args = ap.parse_args()
@@ -296,6 +359,12 @@ def main():
         roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
                                       if v[1] > 0}
 
+    ctx.close()
+    learned = None
+    if not args.no_learned:
+        print("[bench] learned vs plain implicit guess", file=sys.stderr, flush=True)
+        learned = learned_vs_plain(G, args.learned_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -317,9 +386,9 @@ def main():
         "h_error": herr_percentiles(d1["herr_hist"]),
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
         "roofline": roof,
+        "learned_guess": learned,
         "cpu_baseline": cpu,
     }
-    ctx.close()
     print(json.dumps(out))
 
 

@@ -249,13 +249,74 @@ int grpic_enable_timing(grpic_ctx *ctx, int enable);
 int grpic_get_timings(grpic_ctx *ctx, double *ms, long *count);
 int grpic_reset_timings(grpic_ctx *ctx);
 
-/* ---- learned implicit guess (project extension, not in the paper) ----- */
-#define GRPIC_MLP_NPARAM 5510 /* 14 -> 64 -> 64 -> 6, GELU                */
-/* Parameters packed W1[64][14] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]
- * (FP32; the device keeps BF16 copies of the weights), plus feature
- * normalisation mean[14], inv_std[14] and output scale[6].               */
+/* ---- learned implicit guess (project extension, not in the paper) -----
+ * A 14 -> 64 -> 64 -> 6 GELU network gives the implicit pusher's first
+ * iterate as  base + scale (.) net((x - mean) * inv_std),  where base is the
+ * RK4 result for the hybrid pushers (which compute it anyway) and the Euler
+ * step z^n + dt F(z^n) otherwise, and
+ * x = (r, theta, phi, u_r, u_theta, u_phi, (q/m) D^r, (q/m) D^theta,
+ * (q/m) D^phi, (q/m) B^r, (q/m) B^theta, (q/m) B^phi, alpha, beta^r) at
+ * step n (fields gathered as in the push).
+ * The iteration decides the result (Sec. 2.2.2), so the guess changes only
+ * the number of iterations; a particle whose iteration from it does not
+ * converge is restarted from z^n.  Selected with guess = GRPIC_GUESS_MLP.
+ * Parameters are packed W1[64][14] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]
+ * (FP32 master values; weights are rounded to BF16, nearest even, for the
+ * matrix-core products, which accumulate in FP32; biases stay FP32).      */
+#define GRPIC_MLP_NPARAM 5510
+#define GRPIC_MLP_NIN 14
+#define GRPIC_MLP_NOUT 6
+
+/* Load parameters (host arrays: theta[5510], mean[14], inv_std[14],
+ * scale[6]); the context owns its device copy.  Returns GRPIC_E_INVALID on
+ * a null pointer.                                                          */
 int grpic_mlp_set(grpic_ctx *ctx, const float *theta, const float *mean,
                   const float *inv_std, const float *scale);
+/* Copy the current parameters and normalisation to host arrays of the same
+ * sizes.                                                                   */
+int grpic_mlp_get(grpic_ctx *ctx, float *theta, float *mean, float *inv_std,
+                  float *scale);
+
+/* Training samples.  grpic_mlp_collect(ctx, max_rows > 0) allocates room
+ * for max_rows samples and starts collecting: during each following step
+ * every particle of the implicit queue adds one row, its raw features x
+ * (14 FP32) and the target z^{n+1} - base of its converged iteration
+ * (6 FP32), plus valid = 1 if the iteration converged; the iteration then
+ * starts from the base.  Rows beyond max_rows are dropped.  max_rows = 0
+ * stops collecting (samples are kept).                                    */
+int grpic_mlp_collect(grpic_ctx *ctx, long max_rows);
+int grpic_mlp_num_samples(grpic_ctx *ctx, long *n);
+/* Copy the first n samples (X: n x 14, T: n x 6, valid: n; any may be
+ * NULL); GRPIC_E_INVALID if fewer than n were collected.                  */
+int grpic_mlp_get_samples(grpic_ctx *ctx, long n, float *X, float *T,
+                          unsigned char *valid);
+
+typedef struct grpic_mlp_train_config {
+  long epochs;                /* passes over the samples                     */
+  long batch;                 /* rows per gradient step (>= 64)              */
+  double lr, lr_final;        /* Adam step size, cosine-decayed to lr_final  */
+  double beta1, beta2, eps;   /* Adam moments                                */
+  unsigned long long seed;    /* initialisation and batch order              */
+} grpic_mlp_train_config;
+
+/* Train on the collected samples, on the GPU: feature mean / inv_std and
+ * the output scale (RMS of each target component) from the valid samples,
+ * uniform initialisation in +-1/sqrt(fan_in), then Adam on the mean squared
+ * error of the scaled target, one shuffled pass per epoch.  epoch_loss (may
+ * be NULL) receives the mean batch loss of each epoch.  The trained network
+ * is then the one the learned guess uses.  GRPIC_E_STATE with fewer than 64
+ * samples, GRPIC_E_INVALID for a bad configuration.                       */
+int grpic_mlp_train(grpic_ctx *ctx, const grpic_mlp_train_config *cfg,
+                    double *epoch_loss);
+
+/* The network alone, for checks: Y (n x 6) = net(X) for normalised inputs
+ * X (n x 14), host arrays.  grpic_mlp_loss_grad: loss = mean over rows and
+ * outputs of (net(X) - T)^2 and its gradient with respect to the packed
+ * parameters (grad[5510]).  Both use the same matrix-core kernels as the
+ * guess and the training; GRPIC_E_STATE when no network is loaded.       */
+int grpic_mlp_forward(grpic_ctx *ctx, long n, const float *X, float *Y);
+int grpic_mlp_loss_grad(grpic_ctx *ctx, long n, const float *X,
+                        const float *T, float *grad, double *loss);
 
 #ifdef __cplusplus
 }

@@ -263,3 +263,59 @@ class Context:
         keep = [np.ascontiguousarray(x, dtype=np.float32) for x in (theta, mean, inv_std, scale)]
         assert keep[0].size == MLP_NPARAM and keep[1].size == 14 and keep[3].size == 6
         self._c("grpic_mlp_set", *[k.ctypes.data_as(C.POINTER(C.c_float)) for k in keep])
+
+    def mlp_get(self):
+        theta = np.zeros(MLP_NPARAM, np.float32)
+        mean, inv_std, scale = np.zeros(14, np.float32), np.zeros(14, np.float32), np.zeros(6, np.float32)
+        fp = C.POINTER(C.c_float)
+        self._c("grpic_mlp_get", *[x.ctypes.data_as(fp) for x in (theta, mean, inv_std, scale)])
+        return theta, mean, inv_std, scale
+
+    def mlp_collect(self, max_rows):
+        self._c("grpic_mlp_collect", C.c_long(max_rows))
+
+    def mlp_num_samples(self):
+        n = C.c_long()
+        self._c("grpic_mlp_num_samples", C.byref(n))
+        return n.value
+
+    def mlp_get_samples(self, n=None):
+        n = self.mlp_num_samples() if n is None else n
+        X = np.zeros((n, 14), np.float32)
+        T = np.zeros((n, 6), np.float32)
+        valid = np.zeros(n, np.uint8)
+        fp = C.POINTER(C.c_float)
+        self._c("grpic_mlp_get_samples", C.c_long(n), X.ctypes.data_as(fp),
+                T.ctypes.data_as(fp), valid.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        return X, T, valid
+
+    def mlp_train(self, epochs=8, batch=16384, lr=2e-3, lr_final=2e-5, beta1=0.9,
+                  beta2=0.999, eps=1e-8, seed=1):
+        tc = MlpTrainConfig(epochs, batch, lr, lr_final, beta1, beta2, eps, seed)
+        loss = np.zeros(epochs)
+        self._c("grpic_mlp_train", C.byref(tc), _dp(loss))
+        return loss
+
+    def mlp_forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 14)
+        Y = np.zeros((X.shape[0], 6), np.float32)
+        fp = C.POINTER(C.c_float)
+        self._c("grpic_mlp_forward", C.c_long(X.shape[0]), X.ctypes.data_as(fp),
+                Y.ctypes.data_as(fp))
+        return Y
+
+    def mlp_loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 14)
+        T = np.ascontiguousarray(T, dtype=np.float32).reshape(-1, 6)
+        g = np.zeros(MLP_NPARAM, np.float32)
+        loss = C.c_double()
+        fp = C.POINTER(C.c_float)
+        self._c("grpic_mlp_loss_grad", C.c_long(X.shape[0]), X.ctypes.data_as(fp),
+                T.ctypes.data_as(fp), g.ctypes.data_as(fp), C.byref(loss))
+        return loss.value, g
+
+
+class MlpTrainConfig(C.Structure):
+    _fields_ = [("epochs", C.c_long), ("batch", C.c_long), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("seed", C.c_uint64)]

@@ -42,25 +42,6 @@ int guarded(grpic_ctx* c, F&& f) {
   }
 }
 
-template <class T>
-T* dalloc(size_t n) {
-  if (n == 0) n = 1;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(GRPIC_E_OOM, std::string("hipMalloc of ") +
-                                 std::to_string(n * sizeof(T)) + " bytes: " +
-                                 hipGetErrorString(e));
-  }
-  return static_cast<T*>(p);
-}
-
-template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
 
 // Courant limit of the leapfrog on this grid: the smallest
 // 1 / sqrt((c_r/dr)^2 + (c_th/dth)^2) over the nodes, with the coordinate
@@ -148,8 +129,8 @@ void alloc_particles(grpic_ctx* c, long cap) {
     c->seg_cap = (unsigned)(((blocks + kQueueSegs - 1) / kQueueSegs) * 256);
     size_t qlen = (size_t)c->seg_cap * kQueueSegs;
     c->queue = dalloc<int>(qlen);
-    if (c->cfg.guess != GRPIC_GUESS_PLAIN)
-      for (int i = 0; i < 6; ++i) c->gz[i] = dalloc<double>(qlen);
+    // first iterates (RK4 result, learned or collected Euler guess)
+    for (int i = 0; i < 6; ++i) c->gz[i] = dalloc<double>(qlen);
   }
   c->cap = cap;
 }
@@ -851,7 +832,7 @@ int grpic_step(grpic_ctx* c, int nsteps) {
   return guarded(c, [&] {
     check_ctx(c);
     if (nsteps < 0) throw Error(GRPIC_E_INVALID, "nsteps must be >= 0");
-    if (c->cfg.guess == GRPIC_GUESS_MLP && !c->mlp_ready)
+    if (c->cfg.guess == GRPIC_GUESS_MLP && !c->mlp_ready && !mlp_collecting(c))
       throw Error(GRPIC_E_STATE, "learned guess selected but no network set");
     for (int s = 0; s < nsteps; ++s) run_step(c);
   });
@@ -938,6 +919,68 @@ int grpic_mlp_set(grpic_ctx* c, const float* theta, const float* mean,
     drop_graphs(c);
     mlp_upload(c, theta, mean, inv_std, scale);
     c->mlp_ready = true;
+  });
+}
+
+int grpic_mlp_get(grpic_ctx* c, float* theta, float* mean, float* inv_std, float* scale) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!theta || !mean || !inv_std || !scale) throw Error(GRPIC_E_INVALID, "null pointer");
+    if (!c->mlp_ready) throw Error(GRPIC_E_STATE, "no network loaded");
+    mlp_download(c, theta, mean, inv_std, scale);
+  });
+}
+
+int grpic_mlp_collect(grpic_ctx* c, long max_rows) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (max_rows < 0) throw Error(GRPIC_E_INVALID, "negative sample count");
+    if (max_rows > 0 && c->cfg.pusher == GRPIC_PUSH_RK4)
+      throw Error(GRPIC_E_STATE, "the RK4 pusher has no implicit pass to sample");
+    drop_graphs(c);
+    mlp_collect_start(c, max_rows);
+  });
+}
+
+int grpic_mlp_num_samples(grpic_ctx* c, long* n) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!n) throw Error(GRPIC_E_INVALID, "null pointer");
+    *n = mlp_num_samples(c);
+  });
+}
+
+int grpic_mlp_get_samples(grpic_ctx* c, long n, float* X, float* T, unsigned char* valid) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (n < 0) throw Error(GRPIC_E_INVALID, "negative sample count");
+    mlp_get_samples(c, n, X, T, valid);
+  });
+}
+
+int grpic_mlp_train(grpic_ctx* c, const grpic_mlp_train_config* tc, double* epoch_loss) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!tc) throw Error(GRPIC_E_INVALID, "null pointer");
+    drop_graphs(c);
+    mlp_train(c, tc, epoch_loss);
+  });
+}
+
+int grpic_mlp_forward(grpic_ctx* c, long n, const float* X, float* Y) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (n < 0 || (n > 0 && (!X || !Y))) throw Error(GRPIC_E_INVALID, "bad arguments");
+    mlp_forward_rows(c, n, X, Y);
+  });
+}
+
+int grpic_mlp_loss_grad(grpic_ctx* c, long n, const float* X, const float* T, float* grad,
+                        double* loss) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (n <= 0 || !X || !T || !grad || !loss) throw Error(GRPIC_E_INVALID, "bad arguments");
+    mlp_loss_grad(c, n, X, T, grad, loss);
   });
 }
 

@@ -176,11 +176,50 @@ void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
 void launch_guess(grpic_ctx* c);
 void mlp_upload(grpic_ctx* c, const float* theta, const float* mean,
                 const float* inv_std, const float* scale);
+void mlp_download(grpic_ctx* c, float* theta, float* mean, float* inv_std,
+                  float* scale);
 void mlp_free(grpic_ctx* c);
+// training-sample collection by the implicit pass
+struct CollectView {
+  float* T = nullptr;  // targets, cap x 6 (nullptr: not collecting)
+  uint8_t* valid = nullptr;
+  const unsigned long long* rows = nullptr;  // rows collected before this step
+  long cap = 0;
+};
+bool mlp_collecting(grpic_ctx* c);
+CollectView mlp_collect_view(grpic_ctx* c);
+void mlp_collect_start(grpic_ctx* c, long max_rows);
+void mlp_collect_advance(grpic_ctx* c);
+long mlp_num_samples(grpic_ctx* c);
+void mlp_get_samples(grpic_ctx* c, long n, float* X, float* T, uint8_t* valid);
+void mlp_train(grpic_ctx* c, const grpic_mlp_train_config* tc, double* epoch_loss);
+void mlp_forward_rows(grpic_ctx* c, long n, const float* X, float* Y);
+void mlp_loss_grad(grpic_ctx* c, long n, const float* X, const float* T, float* grad,
+                   double* loss);
 
 // timing helpers (api.hip)
 void time_begin(grpic_ctx* c, int kid, hipEvent_t* a);
 void time_end(grpic_ctx* c, int kid, hipEvent_t a);
+
+template <class T>
+T* dalloc(size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(GRPIC_E_OOM, std::string("hipMalloc of ") +
+                                 std::to_string(n * sizeof(T)) + " bytes: " +
+                                 hipGetErrorString(e));
+  }
+  return static_cast<T*>(p);
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
 
 inline unsigned grid_for(long n, int block) {
   long g = (n + block - 1) / block;

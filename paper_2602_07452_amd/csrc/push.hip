@@ -13,6 +13,7 @@
 //    the concatenated segments at a time from a device cursor until the
 //    queue is drained.
 #include "deposit_device.hpp"
+#include "queue_device.hpp"
 
 namespace grpic {
 
@@ -34,6 +35,8 @@ struct PushArgs {
   int* queue;       // kQueueSegs segments of seg_cap entries
   unsigned seg_cap;
   Stats* st;
+  int use_gz;       // the implicit pass starts from gz (else from z^n)
+  CollectView col;  // training-sample collection (col.T == nullptr: off)
 };
 
 struct LocalStats {
@@ -392,39 +395,14 @@ void k_push_explicit(PushArgs A) {
     unsigned slot = seg * A.seg_cap + s_base + s_off[wave] +
                     (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
     A.queue[slot] = (int)k;
-    if (A.guess == GRPIC_GUESS_RK4) {
+    // first iterate (RK4 result; the base of the learned guess in the hybrid)
+    if (A.use_gz && (A.guess == GRPIC_GUESS_RK4 || A.pusher == GRPIC_PUSH_HYB1 ||
+                     A.pusher == GRPIC_PUSH_HYB2)) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
     }
   }
   stats_flush(ls, A.st);
-}
-
-// exclusive prefix of the queue-segment lengths in LDS (blockDim == kQueueSegs)
-__device__ __forceinline__ unsigned segment_prefix(const Stats* st, unsigned* pref) {
-  const int t = threadIdx.x;
-  pref[t + 1] = st->seg_count[t];
-  if (t == 0) pref[0] = 0;
-  __syncthreads();
-  for (int d = 1; d < kQueueSegs; d <<= 1) {
-    unsigned v = (t + 1 > d) ? pref[t + 1 - d] : 0u;
-    __syncthreads();
-    pref[t + 1] += v;
-    __syncthreads();
-  }
-  return pref[kQueueSegs];
-}
-
-// queue slot of the v-th entry counted across segments
-__device__ __forceinline__ unsigned virtual_slot(const unsigned* pref, unsigned v,
-                                                 unsigned seg_cap) {
-  int lo = 0, hi = kQueueSegs;  // pref[lo] <= v < pref[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (pref[mid] <= v) lo = mid;
-    else hi = mid;
-  }
-  return (unsigned)lo * seg_cap + (v - pref[lo]);
 }
 
 // ------------------------------------------------------- implicit pass
@@ -451,23 +429,35 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       double z[6], zk[6];
       load_z(P, k, z);
       double qm = (double)P.qm[k];
-      if (A.guess == GRPIC_GUESS_PLAIN) {
+      if (!A.use_gz) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = z[i];
       } else {
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = A.gz[i][slot];
       }
-      int it;
+      const bool ham = HAM && qm == 0.0 && A.pusher != GRPIC_PUSH_IMR;
       double Wq = 0.0;
-      if (HAM && qm == 0.0 && A.pusher != GRPIC_PUSH_IMR)
-        it = ham_dg(A, z, zk);
-      else
-        it = imr<GRID>(A, qm, z, zk, &Wq);
+      int it = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, zk, &Wq);
+      if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
+        // no convergence from the learned guess: restart from z^n
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zk[i] = z[i];
+        int it2 = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, zk, &Wq);
+        it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
+      }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
       if (it < 0) {
         fl |= F_NOCONV;
         it = -it;
+      }
+      if (A.col.T) {  // training sample: converged step minus the Euler start
+        unsigned long long row = *A.col.rows + v;
+        if (row < (unsigned long long)A.col.cap) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) A.col.T[row * 6 + i] = (float)(zk[i] - A.gz[i][slot]);
+          A.col.valid[row] = (fl & F_NOCONV) ? 0 : 1;
+        }
       }
       double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
       double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq);
@@ -520,6 +510,8 @@ static PushArgs make_args(grpic_ctx* c) {
   A.queue = c->queue;
   A.seg_cap = c->seg_cap;
   A.st = c->stats;
+  A.col = mlp_collect_view(c);
+  A.use_gz = (A.guess != GRPIC_GUESS_PLAIN || A.col.T) ? 1 : 0;
   return A;
 }
 
@@ -538,7 +530,8 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   time_end(c, GRPIC_K_PUSH, ev);
   bool implicit = c->cfg.pusher != GRPIC_PUSH_RK4;
   if (!implicit) return;
-  if (c->cfg.guess == GRPIC_GUESS_MLP) launch_guess(c);
+  const bool collect = A.col.T != nullptr;
+  if (c->cfg.guess == GRPIC_GUESS_MLP || collect) launch_guess(c);
   int dev_cus = c->num_cus;
   int waves = c->cfg.persistent_waves > 0 ? c->cfg.persistent_waves : 8;
   unsigned blocks = (unsigned)((long)dev_cus * waves / 4);
@@ -555,6 +548,7 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
                        c->stream, A);
   GRPIC_HIP(hipGetLastError());
   time_end(c, GRPIC_K_IMPLICIT, ev);
+  if (collect) mlp_collect_advance(c);
 }
 
 void launch_push(grpic_ctx* c) {
