@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch settings (no autotuner trials)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain guess comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
@@ -311,6 +313,11 @@ def main():
     ctx.use_graph(bool(args.graph))
     ctx.step(args.warmup)
     ctx.sync()
+    tune = None
+    if not args.no_autotune:
+        # launch settings picked by the autotuner (its trials are untimed steps)
+        tune = ctx.autotune(3)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     n_alive = ctx.diagnostics()["alive"] or W["n"]
     ctx.enable_timing(not args.graph)
     ctx.reset_timings()
@@ -386,6 +393,7 @@ def main():
         "h_error": herr_percentiles(d1["herr_hist"]),
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
         "roofline": roof,
+        "autotune": tune,
         "learned_guess": learned,
         "cpu_baseline": cpu,
     }

@@ -249,6 +249,27 @@ int grpic_enable_timing(grpic_ctx *ctx, int enable);
 int grpic_get_timings(grpic_ctx *ctx, double *ms, long *count);
 int grpic_reset_timings(grpic_ctx *ctx);
 
+/* ---- autotuner (project extension) ------------------------------------
+ * Times the step under candidate launch settings and keeps the fastest, by
+ * coordinate search: sort tile (tile_r x tile_th in {16x16, 32x16, 32x32,
+ * 64x16, 64x32}; grid contexts), implicit-pass waves per CU {4, 8, 16, 32}
+ * (implicit pushers), explicit-push waves per SIMD {0 = compiler choice, 4}.
+ * Each candidate runs one untimed and trial_steps timed steps (no re-sort
+ * inside a trial): the trials are real steps of the simulation, which
+ * advances by them.  Results are identical for every setting (the deposit
+ * is order-independent), only the speed changes.  Needs loaded particles
+ * (GRPIC_E_STATE otherwise); trial_steps >= 1.                           */
+typedef struct grpic_tune_result {
+  int tile_r, tile_th;      /* chosen sort tile                          */
+  int persistent_waves;     /* chosen implicit-pass waves per CU         */
+  int push_waves_per_simd;  /* chosen explicit-push occupancy            */
+  int trials;               /* settings timed                            */
+  int steps;                /* simulation steps taken by the trials      */
+  double ms_start;          /* ms per step of the starting setting       */
+  double ms_best;           /* ms per step of the chosen setting         */
+} grpic_tune_result;
+int grpic_autotune(grpic_ctx *ctx, int trial_steps, grpic_tune_result *out);
+
 /* ---- learned implicit guess (project extension, not in the paper) -----
  * A 14 -> 64 -> 64 -> 6 GELU network gives the implicit pusher's first
  * iterate as  base + scale (.) net((x - mean) * inv_std),  where base is the

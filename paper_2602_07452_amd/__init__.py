@@ -264,6 +264,15 @@ class Context:
         assert keep[0].size == MLP_NPARAM and keep[1].size == 14 and keep[3].size == 6
         self._c("grpic_mlp_set", *[k.ctypes.data_as(C.POINTER(C.c_float)) for k in keep])
 
+    # -- autotuner
+    def autotune(self, trial_steps=3):
+        r = TuneResult()
+        self._c("grpic_autotune", C.c_int(trial_steps), C.byref(r))
+        self.cfg.tile_r, self.cfg.tile_th = r.tile_r, r.tile_th
+        self.cfg.persistent_waves = r.persistent_waves
+        self.cfg.push_waves_per_simd = r.push_waves_per_simd
+        return {f[0]: getattr(r, f[0]) for f in TuneResult._fields_}
+
     def mlp_get(self):
         theta = np.zeros(MLP_NPARAM, np.float32)
         mean, inv_std, scale = np.zeros(14, np.float32), np.zeros(14, np.float32), np.zeros(6, np.float32)
@@ -313,6 +322,12 @@ class Context:
         self._c("grpic_mlp_loss_grad", C.c_long(X.shape[0]), X.ctypes.data_as(fp),
                 T.ctypes.data_as(fp), g.ctypes.data_as(fp), C.byref(loss))
         return loss.value, g
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("tile_r", C.c_int), ("tile_th", C.c_int), ("persistent_waves", C.c_int),
+                ("push_waves_per_simd", C.c_int), ("trials", C.c_int), ("steps", C.c_int),
+                ("ms_start", C.c_double), ("ms_best", C.c_double)]
 
 
 class MlpTrainConfig(C.Structure):

@@ -985,3 +985,125 @@ int grpic_mlp_loss_grad(grpic_ctx* c, long n, const float* X, const float* T, fl
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- autotuner
+namespace {
+
+double time_steps(grpic_ctx* c, int k) {
+  run_step(c);  // untimed: graph capture, caches
+  GRPIC_HIP(hipStreamSynchronize(c->stream));
+  hipEvent_t a, b;
+  GRPIC_HIP(hipEventCreate(&a));
+  GRPIC_HIP(hipEventCreate(&b));
+  float ms = 0.0f;
+  try {
+    GRPIC_HIP(hipEventRecord(a, c->stream));
+    for (int s = 0; s < k; ++s) run_step(c);
+    GRPIC_HIP(hipEventRecord(b, c->stream));
+    GRPIC_HIP(hipEventSynchronize(b));
+    GRPIC_HIP(hipEventElapsedTime(&ms, a, b));
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return (double)ms / k;
+}
+
+bool set_tiles(grpic_ctx* c, int tr, int tt) {
+  long ntr = (c->nr + tr - 1) / tr, ntt = (c->nth + tt - 1) / tt;
+  if (ntr * ntt > 16384) return false;
+  GRPIC_HIP(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  dfree(c->tile_count);
+  dfree(c->tile_offset);
+  c->cfg.tile_r = tr;
+  c->cfg.tile_th = tt;
+  c->ntiles = (int)(ntr * ntt);
+  c->tile_count = dalloc<int>(c->ntiles + 1);
+  c->tile_offset = dalloc<int>(c->ntiles + 1);
+  launch_fill(c, c->tile_count, sizeof(int) * (c->ntiles + 1));
+  launch_sort(c);
+  return true;
+}
+
+}  // namespace
+
+int grpic_autotune(grpic_ctx* c, int trial_steps, grpic_tune_result* out) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!out || trial_steps < 1) throw Error(GRPIC_E_INVALID, "bad arguments");
+    if (c->n == 0) throw Error(GRPIC_E_STATE, "no particles loaded");
+    std::memset(out, 0, sizeof(*out));
+    const long steps0 = c->steps;
+    const int sort_every = c->cfg.sort_every;
+    c->cfg.sort_every = 0;  // no re-sort inside the trials
+    try {
+      const bool grid = c->cfg.field_mode != GRPIC_FIELDS_NONE;
+      const bool implicit = c->cfg.pusher != GRPIC_PUSH_RK4;
+      if (grid) set_tiles(c, c->cfg.tile_r, c->cfg.tile_th);
+      double best = time_steps(c, trial_steps);
+      out->ms_start = best;
+      out->trials = 1;
+      if (grid) {
+        const int cand[5][2] = {{16, 16}, {32, 16}, {32, 32}, {64, 16}, {64, 32}};
+        int br = c->cfg.tile_r, bt = c->cfg.tile_th;
+        for (auto& t : cand) {
+          if (t[0] == br && t[1] == bt) continue;
+          if (!set_tiles(c, t[0], t[1])) continue;
+          double ms = time_steps(c, trial_steps);
+          ++out->trials;
+          if (ms < best) {
+            best = ms;
+            br = t[0];
+            bt = t[1];
+          }
+        }
+        set_tiles(c, br, bt);
+      }
+      if (implicit) {
+        int bw = c->cfg.persistent_waves;
+        for (int w : {4, 8, 16, 32}) {
+          if (w == bw) continue;
+          c->cfg.persistent_waves = w;
+          drop_graphs(c);
+          double ms = time_steps(c, trial_steps);
+          ++out->trials;
+          if (ms < best) {
+            best = ms;
+            bw = w;
+          }
+        }
+        c->cfg.persistent_waves = bw;
+      }
+      {
+        int bp = c->cfg.push_waves_per_simd;
+        for (int p : {0, 4}) {
+          if (p == bp) continue;
+          c->cfg.push_waves_per_simd = p;
+          drop_graphs(c);
+          double ms = time_steps(c, trial_steps);
+          ++out->trials;
+          if (ms < best) {
+            best = ms;
+            bp = p;
+          }
+        }
+        c->cfg.push_waves_per_simd = bp;
+      }
+      drop_graphs(c);
+      out->tile_r = c->cfg.tile_r;
+      out->tile_th = c->cfg.tile_th;
+      out->persistent_waves = c->cfg.persistent_waves;
+      out->push_waves_per_simd = c->cfg.push_waves_per_simd;
+      out->ms_best = best;
+      out->steps = (int)(c->steps - steps0);
+    } catch (...) {
+      c->cfg.sort_every = sort_every;
+      throw;
+    }
+    c->cfg.sort_every = sort_every;
+  });
+}

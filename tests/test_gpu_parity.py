@@ -261,6 +261,40 @@ def test_full_step_is_deterministic():
     assert np.array_equal(Pa["z"], Pb["z"])
 
 
+def _rows(P):
+    """Particle records in a canonical order (the tile sort permutes them)."""
+    M = np.column_stack([P["z"], P["qm"], P["w"], P["H0"], P["flags"], P["iters"]])
+    return M[np.lexsort(M.T[::-1])]
+
+
+def test_autotune_keeps_results():
+    """The autotuner only changes launch settings and the particle order: the
+    grids after its trial steps equal, bit for bit, those of the same number
+    of steps with the default settings, and so do the particle records."""
+    cfg = _pic_cfg(n=6000, nr=64, nth=48)
+    outs, steps = [], None
+    for tune in (True, False):
+        with G.Context(cfg) as ctx:
+            ctx.set_fields_wald(1.0)
+            ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 7, rplus(cfg.a),
+                               18.0, cfg.theta0, np.pi - cfg.theta0, 0.1, w=2e-3)
+            if tune:
+                r = ctx.autotune(1)
+                steps = r["steps"]
+                assert r["trials"] >= 8 and r["ms_best"] <= r["ms_start"]
+                assert (r["tile_r"], r["tile_th"]) in ((16, 16), (32, 16), (32, 32), (64, 16),
+                                                      (64, 32))
+                assert r["persistent_waves"] in (4, 8, 16, 32)
+            else:
+                ctx.step(steps)
+            outs.append(_gpu_state(ctx))
+    (Sa, Pa), (Sb, Pb) = outs
+    for lev in Sa:
+        for a, b in zip(Sa[lev], Sb[lev]):
+            assert np.array_equal(a, b)
+    assert np.array_equal(_rows(Pa), _rows(Pb))
+
+
 def test_graph_replay_equals_eager():
     cfg = _pic_cfg(n=3000)
     outs = []
