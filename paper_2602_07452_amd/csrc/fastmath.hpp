@@ -16,16 +16,15 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(y, e, y);
 }
 
-// sqrt(x) for finite x > 0 away from the denormal range: hardware estimate
-// of 1/sqrt(x) refined by Goldschmidt's coupled iteration for sqrt(x) and
-// 1/(2 sqrt(x)), with a final residual correction.
+// sqrt(x) for finite x > 0 away from the denormal range: the hardware
+// estimate of 1/sqrt(x) (relative error below 2^-24) refined by one step of
+// Goldschmidt's coupled iteration for sqrt(x) and 1/(2 sqrt(x)) (error ~2^-48)
+// and a final residual correction (Newton step on s^2 = x), which rounds
+// correctly in practice.
 __device__ __forceinline__ double fsqrt(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double s = x * y, h = 0.5 * y;
   double r = fma(-s, h, 0.5);
-  s = fma(s, r, s);
-  h = fma(h, r, h);
-  r = fma(-s, h, 0.5);
   s = fma(s, r, s);
   h = fma(h, r, h);
   r = fma(-s, s, x);
@@ -65,6 +64,35 @@ __device__ __forceinline__ void fsincos(double x, double* sn, double* cs) {
   double c = (q & 1) ? ps : pc;
   *sn = (q & 2) ? -s : s;
   *cs = ((q + 1) & 2) ? -c : c;
+}
+
+// sin and cos of t from those of a nearby angle t0 (s0, c0): with d = t - t0
+// (exact for nearby arguments), Taylor series of sin d and cos d - 1 to d^11
+// and d^12 (truncation below 1e-18 for |d| <= 0.2) and the angle-addition
+// formulas arranged as corrections to s0, c0.  Farther angles use fsincos.
+__device__ __forceinline__ void sincos_near(double t, double t0, double s0,
+                                            double c0, double* sn, double* cs) {
+  const double d = t - t0;
+  if (fabs(d) > 0.2) {
+    fsincos(t, sn, cs);
+    return;
+  }
+  const double d2 = d * d;
+  double ps = -1.0 / 39916800.0;
+  ps = 1.0 / 362880.0 + d2 * ps;
+  ps = -1.0 / 5040.0 + d2 * ps;
+  ps = 1.0 / 120.0 + d2 * ps;
+  ps = -1.0 / 6.0 + d2 * ps;
+  const double sd = fma(d * d2, ps, d);  // sin d
+  double pc = 1.0 / 479001600.0;
+  pc = -1.0 / 3628800.0 + d2 * pc;
+  pc = 1.0 / 40320.0 + d2 * pc;
+  pc = -1.0 / 720.0 + d2 * pc;
+  pc = 1.0 / 24.0 + d2 * pc;
+  pc = -0.5 + d2 * pc;
+  const double cm1 = d2 * pc;            // cos d - 1
+  *sn = fma(s0, cm1, fma(c0, sd, s0));
+  *cs = fma(c0, cm1, fma(-s0, sd, c0));
 }
 
 }  // namespace grpic

@@ -31,9 +31,8 @@ struct DMet {  // [0] = d/dr, [1] = d/dtheta
 
 __device__ __forceinline__ double rcp(double x) { return frcp(x); }
 
-__device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
-  double s, c;
-  fsincos(th, &s, &c);
+// metric at (r, theta) given s = sin theta, c = cos theta
+__device__ __forceinline__ void metric_sc(double a, double r, double s, double c, Met& m) {
   double a2 = a * a, s2 = s * s;
   double rho2 = r * r + a2 * c * c;
   double S = rho2 + 2.0 * r;
@@ -54,11 +53,15 @@ __device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
   m.sg = fabs(s) * fsqrt(rho2 * S);
 }
 
-// metric plus derivatives of alpha, beta^r and gamma^ij
-__device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
-                                         DMet& d) {
+__device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
   double s, c;
   fsincos(th, &s, &c);
+  metric_sc(a, r, s, c, m);
+}
+
+// metric plus derivatives of alpha, beta^r and gamma^ij
+__device__ __forceinline__ void metric_d_sc(double a, double r, double s, double c,
+                                            Met& m, DMet& d) {
   double a2 = a * a, s2 = s * s, sc = s * c;
   double rho2 = r * r + a2 * c * c;
   double S = rho2 + 2.0 * r;
@@ -92,6 +95,13 @@ __device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
     d.dpp[k] = -(dr2[k] * s2 + rho2 * ds2[k]) * (i4 * is2 * is2);
     d.drp[k] = -a * dr2[k] * i4;
   }
+}
+
+__device__ __forceinline__ void metric_d(double a, double r, double th, Met& m,
+                                         DMet& d) {
+  double s, c;
+  fsincos(th, &s, &c);
+  metric_d_sc(a, r, s, c, m, d);
 }
 
 // Divided differences [f(x1) - f(x0)] / (x1^k - x0^k) of f = alpha, beta^r,
@@ -135,14 +145,20 @@ __device__ __forceinline__ void metric_dd(double a, int k, double r0,
   q[5] = a * d_irho2;
 }
 
-// e = alpha Gamma - beta^r u_r
-__device__ __forceinline__ double energy(double a, const double* z) {
+// e = alpha Gamma - beta^r u_r, with s, c = sin, cos of z[1]
+__device__ __forceinline__ double energy_sc(double a, const double* z, double s, double c) {
   Met m;
-  metric(a, z[0], z[1], m);
+  metric_sc(a, z[0], s, c, m);
   double ur = z[3], ut = z[4], up = z[5];
   double q = m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
              2.0 * m.irp * ur * up;
   return m.alpha * fsqrt(1.0 + q) - m.betar * ur;
+}
+
+__device__ __forceinline__ double energy(double a, const double* z) {
+  double s, c;
+  fsincos(z[1], &s, &c);
+  return energy_sc(a, z, s, c);
 }
 
 // ---------------------------------------------------------------- gather

@@ -70,47 +70,54 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
 }
 
 // --------------------------------------------------------------- F(z)
+// F at z, with s, c = sin, cos of z[1]
 template <bool GRID>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
-                                     const double* z, double* f, double* pw,
-                                     double* e = nullptr) {
+                                     const double* z, double s, double c, double* f,
+                                     double* pw, double* e = nullptr) {
   Met m;
   DMet d;
-  metric_d(A.a, z[0], z[1], m, d);
+  metric_d_sc(A.a, z[0], s, c, m, d);
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
   if (GRID && qm != 0.0) gather(A.g, A.f, z[0], z[1], rcp(m.sg), D, B);
   rhs(qm, z, m, d, D, B, f, pw, e);
 }
 
 // RK4; *e0 = energy e at z (from the first stage)
+// classical RK4 with the fields re-gathered at every stage; s0, c0 (out):
+// sin, cos of z[1], from which the stage angles are reached by short series
 template <bool GRID>
 __device__ __forceinline__ void rk4(const PushArgs& A, double qm,
                                     const double* z, double* out, double* Wq,
-                                    double* e0) {
+                                    double* e0, double* s0, double* c0) {
   const double dt = A.dt, hdt = 0.5 * A.dt;
-  double k[6], acc[6], y[6], p, pacc;
-  eval<GRID>(A, qm, z, k, &p, e0);
+  double k[6], acc[6], y[6], p, pacc, s, c;
+  fsincos(z[1], s0, c0);
+  eval<GRID>(A, qm, z, *s0, *c0, k, &p, e0);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] = k[i];
     y[i] = z[i] + hdt * k[i];
   }
   pacc = p;
-  eval<GRID>(A, qm, y, k, &p);
+  sincos_near(y[1], z[1], *s0, *c0, &s, &c);
+  eval<GRID>(A, qm, y, s, c, k, &p);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
     y[i] = z[i] + hdt * k[i];
   }
   pacc += 2.0 * p;
-  eval<GRID>(A, qm, y, k, &p);
+  sincos_near(y[1], z[1], *s0, *c0, &s, &c);
+  eval<GRID>(A, qm, y, s, c, k, &p);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
     y[i] = z[i] + dt * k[i];
   }
   pacc += 2.0 * p;
-  eval<GRID>(A, qm, y, k, &p);
+  sincos_near(y[1], z[1], *s0, *c0, &s, &c);
+  eval<GRID>(A, qm, y, s, c, k, &p);
   const double c6 = dt / 6.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) out[i] = z[i] + c6 * (acc[i] + k[i]);
@@ -130,14 +137,15 @@ __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
 
 // implicit midpoint rule by fixed-point iteration; zk: guess in, result out
 template <bool GRID>
-__device__ int imr(const PushArgs& A, double qm, const double* z, double* zk,
-                   double* Wq) {
+__device__ int imr(const PushArgs& A, double qm, const double* z, double s0, double c0,
+                   double* zk, double* Wq) {
   double p = 0.0;
   for (int k = 1; k <= A.kmax; ++k) {
-    double zm[6], f[6], zn[6];
+    double zm[6], f[6], zn[6], sm, cm;
 #pragma unroll
     for (int i = 0; i < 6; ++i) zm[i] = 0.5 * (z[i] + zk[i]);
-    eval<GRID>(A, qm, zm, f, &p);
+    sincos_near(zm[1], z[1], s0, c0, &sm, &cm);
+    eval<GRID>(A, qm, zm, sm, cm, f, &p);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zn[i] = z[i] + A.dt * f[i];
     bool c = small_change(zn, zk, A.tol);
@@ -255,26 +263,34 @@ __device__ int ham_dg(const PushArgs& A, const double* z, double* zk) {
 // ----------------------------------------------------------- switch value
 // neutral: |e - H0| / |H0|; charged: |e' - e - W| / |e| (W: the scheme's
 // quadrature of (q/m) E_i dx^i/dt)
+// zn: the new state; s0, c0: sin, cos of the old angle z0
 __device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
                                                double H0, double e0,
-                                               const double* zn, double Wq) {
-  double e1 = energy(A.a, zn);
+                                               const double* zn, double Wq,
+                                               double z0, double s0, double c0) {
+  double s, c;
+  sincos_near(zn[1], z0, s0, c0, &s, &c);
+  double e1 = energy_sc(A.a, zn, s, c);
   if (qm == 0.0) return fabs(e1 - H0) / fabs(H0);
   return fabs(e1 - e0 - Wq) / fabs(e0);
 }
 
+// histogram bin b = floor(2 (log10 v + 30)) of an energy violation (a
+// diagnostic: FP32 logarithm)
 __device__ __forceinline__ int herr_bin(double v) {
-  if (!(v > 0.0)) return 0;
-  int b = (int)floor(2.0 * (log10(v) + 30.0));
+  if (!(v >= 1e-30)) return 0;
+  float l = __builtin_amdgcn_logf((float)fmin(v, 1e30)) * 0.30102999566398120f;
+  int b = (int)floorf(2.0f * (l + 30.0f));
   return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
 }
 
 // write the step result, apply the particle boundary conditions and (for a
 // deposit) store the old position and the weights of the new one
+// s0, c0: sin, cos of z[1]
 template <bool EVOLVE>
 __device__ void finalize(const PushArgs& A, long k, const double* z,
                          double* out, double herr, int iters, uint8_t fl,
-                         LocalStats& ls) {
+                         LocalStats& ls, double s0, double c0) {
   const ParticleView& P = A.p;
   if (out[0] < A.r_min || out[0] > A.r_max) {
     fl = F_REMOVED;
@@ -317,8 +333,9 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
     if (fl & F_ALIVE) {
       int p, q;
       node_cell(A.g, out[0], out[1], p, q);
-      double W[4];
-      dep_weights(A.g, out[0], out[1], p, q, W);
+      double W[4], st, ct;
+      sincos_near(out[1], z[1], s0, c0, &st, &ct);
+      dep_weights(A.g, out[0], out[1], st, ct, p, q, W);
 #pragma unroll
       for (int c = 0; c < 4; ++c) P.Wn[c][k] = W[c];
       P.celln[k] = q * A.g.nr + p;
@@ -357,9 +374,9 @@ void k_push_explicit(PushArgs A) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
     } else {
-      double Wq, e0;
-      rk4<GRID>(A, qm, z, trial, &Wq, &e0);
-      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq);
+      double Wq, e0, s0, c0;
+      rk4<GRID>(A, qm, z, trial, &Wq, &e0, &s0, &c0);
+      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
         accept = v < A.thr;
@@ -368,7 +385,7 @@ void k_push_explicit(PushArgs A) {
         accept = (v - prev) / (A.dt * fmax(prev, 0x1p-52)) < A.thr;
       }
       if (accept)
-        finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls);
+        finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0);
       else
         enq = true;
     }
@@ -437,13 +454,14 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         for (int i = 0; i < 6; ++i) zk[i] = A.gz[i][slot];
       }
       const bool ham = HAM && qm == 0.0 && A.pusher != GRPIC_PUSH_IMR;
-      double Wq = 0.0;
-      int it = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, zk, &Wq);
+      double Wq = 0.0, s0, c0;
+      fsincos(z[1], &s0, &c0);
+      int it = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, s0, c0, zk, &Wq);
       if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
         // no convergence from the learned guess: restart from z^n
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = z[i];
-        int it2 = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, zk, &Wq);
+        int it2 = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, s0, c0, zk, &Wq);
         it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
       }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
@@ -459,9 +477,9 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
           A.col.valid[row] = (fl & F_NOCONV) ? 0 : 1;
         }
       }
-      double e0 = qm != 0.0 ? energy(A.a, z) : 0.0;
-      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq);
-      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls);
+      double e0 = qm != 0.0 ? energy_sc(A.a, z, s0, c0) : 0.0;
+      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0);
+      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0);
     }
   }
   __syncthreads();
