@@ -101,6 +101,14 @@ WORKLOADS = {
               "Theta=0.1, FDTD + gather + Hyb2 push (RK4 -> IMR) + conserving deposit"),
         a=0.99, nr=1024, nth=1024, r_out=20.0, n=1 << 24, mode="evolve",
         pusher="hyb2", thr=1e-13, theta=0.1, r_abs=18.0),
+    "c5": dict(
+        desc=("full PIC cycle, split-monopole magnetosphere: Kerr a=0.9, 2048x2048 (r,theta) "
+              "grid r in [0.9 r+, 100], absorbing layer from 90, 2^27 e+/e- macro-particles "
+              "uniform in proper volume, Maxwell-Juettner Theta=0.05, FDTD + gather + Hyb2 "
+              "push (RK4 -> IMR, learned guess) + conserving deposit, step replayed as a "
+              "hipGraph"),
+        a=0.9, nr=2048, nth=2048, r_out=100.0, n=1 << 27, mode="evolve", fields="monopole",
+        pusher="hyb2", thr=1e-13, theta=0.05, r_abs=90.0, graph=1, guess="mlp"),
     "c2": dict(
         desc=("charged test particles in the Kerr a=0.9 Wald field (B0=1) on a "
               "512x512 grid, r in [0.9 r+, 50]: 2^20 particles, q/m=+-1, |u|~U[0,1] "
@@ -121,11 +129,15 @@ def make_context(G, W, n=None, push_wps=0):
         pusher=G.PUSH_HYB2, hyb_threshold=W["thr"], max_particles=n,
         r_remove_in=rp, r_remove_out=W["r_out"], reflect=1,
         r_abs=W.get("r_abs", 0.0), chi0=1e4 if evolve else 0.0, lambda_abs=5.0,
-        guess=G.GUESS_RK4, sort_every=W.get("sort_every", 50),
+        guess=G.GUESS_MLP if W.get("guess") == "mlp" else G.GUESS_RK4,
+        sort_every=W.get("sort_every", 50),
         push_waves_per_simd=push_wps)
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
     ctx = G.Context(cfg)
-    ctx.set_fields_wald(1.0)
+    if W.get("fields") == "monopole":
+        ctx.set_fields_split_monopole(1.0, 1e3)
+    else:
+        ctx.set_fields_wald(1.0)
     if evolve:
         # weight: plasma frequency omega_p dt = 0.05 at the mean density
         # (4 pi n q^2/m = omega_p^2, n = N w / V, V ~ proper shell volume)
@@ -158,7 +170,10 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
     import oracle as O
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     g = O.Grid(cfg.a, cfg.nr, cfg.nth, cfg.r_in, cfg.r_out, cfg.theta0)
-    D, B = O.wald_grid(g, 1.0)
+    if W.get("fields") == "monopole":
+        D, B = O.split_monopole_grid(g, 1.0, 1e3)
+    else:
+        D, B = O.wald_grid(g, 1.0)
     G6 = [g.densitize(c, D[c]) for c in range(3)] + [g.densitize(3 + c, B[c]) for c in range(3)]
     evolve = W["mode"] == "evolve"
     if evolve:
@@ -310,7 +325,18 @@ def main():
     ctx, cfg = make_context(G, W, push_wps=args.push_wps)
     print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,
           flush=True)
-    ctx.use_graph(bool(args.graph))
+    graph = bool(args.graph or W.get("graph", 0))
+    mlp_info = None
+    if W.get("guess") == "mlp":
+        # learned guess: trained on the GPU on the converged implicit steps of
+        # the first warmup steps (RK4 result corrected by the network)
+        ctx.mlp_collect(1 << 24)
+        ctx.step(max(args.warmup // 2, 4))
+        ctx.mlp_collect(0)
+        loss = ctx.mlp_train(epochs=8, batch=4096, lr=3e-3, lr_final=3e-5, seed=7)
+        mlp_info = {"samples": ctx.mlp_num_samples(), "loss_first_epoch": float(loss[0]),
+                    "loss_last_epoch": float(loss[-1])}
+    ctx.use_graph(graph)
     ctx.step(args.warmup)
     ctx.sync()
     tune = None
@@ -319,7 +345,7 @@ def main():
         tune = ctx.autotune(3)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     n_alive = ctx.diagnostics()["alive"] or W["n"]
-    ctx.enable_timing(not args.graph)
+    ctx.enable_timing(not graph)
     ctx.reset_timings()
     d0 = ctx.diagnostics()
     t0 = time.perf_counter()
@@ -343,7 +369,7 @@ def main():
         "implicit": iters * FLOP_IMR_ITER + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
     }
     roof = None
-    if not args.graph:
+    if not graph:
         ms = {k: v[0] for k, v in tim.items()}
         dom = max(ms, key=ms.get)
         cnt = max(tim[dom][1], 1)
@@ -385,8 +411,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["desc"], "particles": W["n"], "grid": [W["nr"], W["nth"]],
                    "dt": cfg.dt, "pusher": "Hyb2 (RK4 -> IMR)", "threshold": cfg.hyb_threshold,
-                   "guess": "RK4 result", "fields": "FP32", "particle_state": "FP64",
-                   "graph": bool(args.graph), "sort_every": cfg.sort_every,
+                   "guess": ("RK4 result + learned correction" if mlp_info else "RK4 result"),
+                   "fields": "FP32", "particle_state": "FP64",
+                   "graph": graph, "sort_every": cfg.sort_every,
                    "tile": [cfg.tile_r, cfg.tile_th]},
         "implicit_fraction": impl / max(args.steps * n_alive, 1),
         "mean_implicit_iterations": float(iters / max(impl, 1)),
@@ -394,6 +421,7 @@ def main():
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
         "roofline": roof,
         "autotune": tune,
+        "learned_guess_training": mlp_info,
         "learned_guess": learned,
         "cpu_baseline": cpu,
     }

@@ -201,6 +201,14 @@ int grpic_get_particles(grpic_ctx *ctx, long n, double *r, double *th,
                         double *qm, double *w, double *H0, double *herr,
                         int32_t *flags, int32_t *iters);
 int grpic_num_particles(grpic_ctx *ctx, long *n);
+/* Copy the particles with the given ids (m <= 2^24 distinct ids in
+ * [0, n)): rec receives 10 doubles per id (r, theta, phi, u_r, u_theta,
+ * u_phi, q/m, w, H0, herr), flags and iters (may be NULL) one int each.
+ * For checks of large runs without copying every particle.  Allocates a
+ * temporary id map of n ints on the device.  GRPIC_E_INVALID for ids out of
+ * range or repeated.                                                       */
+int grpic_sample_particles(grpic_ctx *ctx, long m, const long *ids,
+                           double *rec, int32_t *flags, int32_t *iters);
 
 /* ---- stepping ---------------------------------------------------------- */
 /* Advance nsteps steps, asynchronously on the context's stream.           */

@@ -222,6 +222,22 @@ class Context:
         out["z"] = np.stack([out[k] for k in ("r", "th", "ph", "ur", "uth", "uph")], axis=1)
         return out
 
+    def sample_particles(self, ids):
+        """Particle records of the given ids, as get_particles() returns them."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        m = len(ids)
+        rec = np.zeros((m, 10))
+        flags = np.zeros(m, np.int32)
+        iters = np.zeros(m, np.int32)
+        ip = C.POINTER(C.c_int32)
+        self._c("grpic_sample_particles", C.c_long(m), ids.ctypes.data_as(C.POINTER(C.c_long)),
+                _dp(rec), flags.ctypes.data_as(ip), iters.ctypes.data_as(ip))
+        out = {k: np.ascontiguousarray(rec[:, i]) for i, k in enumerate(
+            ("r", "th", "ph", "ur", "uth", "uph", "qm", "w", "H0", "herr"))}
+        out["flags"], out["iters"] = flags, iters
+        out["z"] = rec[:, :6].copy()
+        return out
+
     # -- stepping
     def step(self, nsteps=1):
         self._c("grpic_step", C.c_int(nsteps))

@@ -777,6 +777,51 @@ int grpic_load_particles(grpic_ctx* c, long n, const double* r,
   });
 }
 
+int grpic_sample_particles(grpic_ctx* c, long m, const long* ids, double* rec,
+                           int32_t* flags, int32_t* iters) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (m < 0 || (m > 0 && (!ids || !rec))) throw Error(GRPIC_E_INVALID, "bad arguments");
+    if (m == 0) return;
+    if (m > (1L << 24)) throw Error(GRPIC_E_INVALID, "sample larger than 2^24");
+    std::vector<int> map((size_t)c->n, -1);
+    for (long s = 0; s < m; ++s) {
+      if (ids[s] < 0 || ids[s] >= c->n) throw Error(GRPIC_E_INVALID, "id out of range");
+      if (map[(size_t)ids[s]] >= 0) throw Error(GRPIC_E_INVALID, "repeated id");
+      map[(size_t)ids[s]] = (int)s;
+    }
+    int* dmap = dalloc<int>((size_t)c->n);
+    double* dout = nullptr;
+    int* dfl = nullptr;
+    try {
+      dout = dalloc<double>((size_t)m * 10);
+      dfl = dalloc<int>((size_t)m * 2);
+      GRPIC_HIP(hipMemcpyAsync(dmap, map.data(), sizeof(int) * (size_t)c->n,
+                               hipMemcpyHostToDevice, c->stream));
+      launch_sample(c, dmap, dout, dfl);
+      GRPIC_HIP(hipMemcpyAsync(rec, dout, sizeof(double) * 10 * (size_t)m,
+                               hipMemcpyDeviceToHost, c->stream));
+      std::vector<int> fl((size_t)m * 2);
+      GRPIC_HIP(hipMemcpyAsync(fl.data(), dfl, sizeof(int) * 2 * (size_t)m,
+                               hipMemcpyDeviceToHost, c->stream));
+      GRPIC_HIP(hipStreamSynchronize(c->stream));
+      for (long s = 0; s < m; ++s) {
+        if (flags) flags[s] = fl[2 * s];
+        if (iters) iters[s] = fl[2 * s + 1];
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(c->stream);
+      dfree(dmap);
+      dfree(dout);
+      dfree(dfl);
+      throw;
+    }
+    dfree(dmap);
+    dfree(dout);
+    dfree(dfl);
+  });
+}
+
 int grpic_num_particles(grpic_ctx* c, long* n) {
   return guarded(c, [&] {
     check_ctx(c);

@@ -171,6 +171,7 @@ void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,
                            const double* mj_table, int mj_k, double mj_h);
 void launch_energy_H0(grpic_ctx* c);
 void launch_sort(grpic_ctx* c);
+void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
                        double* pbz);
 void launch_guess(grpic_ctx* c);

@@ -252,6 +252,39 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
   }
 }
 
+// ------------------------------------------------------------ sampling
+// records of the particles whose id has a slot in the map (map[id] = slot
+// of the sample, -1 otherwise); out holds 10 doubles per slot (r, theta,
+// phi, u_r, u_theta, u_phi, q/m, w, H0, herr) and fl 2 ints (flags, iters)
+__global__ __launch_bounds__(256) void k_sample(ParticleView P, const int* map, double* out,
+                                                int* fl) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  int s = map[P.id[k]];
+  if (s < 0) return;
+  double* o = out + (long)s * 10;
+  o[0] = P.r[k];
+  o[1] = P.th[k];
+  o[2] = P.ph[k];
+  o[3] = P.ur[k];
+  o[4] = P.uth[k];
+  o[5] = P.uph[k];
+  o[6] = (double)P.qm[k];
+  o[7] = P.w[k];
+  o[8] = P.H0[k];
+  o[9] = P.herr[k];
+  fl[2 * s] = P.flags[k];
+  fl[2 * s + 1] = P.iters[k];
+}
+
+void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl) {
+  ParticleView P = c->pv;
+  P.n = c->n;
+  hipLaunchKernelGGL(k_sample, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream, P, map, out,
+                     fl);
+  GRPIC_HIP(hipGetLastError());
+}
+
 void launch_sort(grpic_ctx* c) {
   if (c->n == 0 || c->nr == 0) return;
   hipEvent_t ev;
