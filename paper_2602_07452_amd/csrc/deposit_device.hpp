@@ -15,7 +15,7 @@ __device__ __forceinline__ void node_cell(const GridView& g, double r,
   float lr = radial_coord(g, r);
   double lt = (th - g.th0) * g.inv_dth;
   p = refine(g.rn, g.nr + 1, r, (int)floorf(lr));
-  q = refine(g.tn, g.nth + 1, th, (int)floor(lt));
+  q = theta_cell<false>(g, th, lt, g.nth + 1);
 }
 
 // sin and cos of t0 + j h, j = 0..3, from those of t0 and of the small step
@@ -43,7 +43,8 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
                                             double th, double st, double ct,
                                             int p, int q, double* W) {
   const double a2 = g.a * g.a;
-  double ra = g.rn[p], rb = g.rn[p + 1], ta = g.tn[q], tb = g.tn[q + 1];
+  double ra = g.rn[p], rb = g.rn[p + 1];
+  double ta = theta_node(g, q), tb = theta_node(g, q + 1);
   double h1r = (r - ra) * (1.0 / 3.0), h2r = (rb - r) * (1.0 / 3.0);
   double h1t = (th - ta) * (1.0 / 3.0), h2t = (tb - th) * (1.0 / 3.0);
   // 7 radii: ra + i h1r (i = 0..2), r, r + i h2r (i = 1..3); same for theta

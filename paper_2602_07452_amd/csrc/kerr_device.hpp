@@ -217,52 +217,104 @@ __device__ __forceinline__ double clamp01(double f) {
   return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
 }
 
-struct Stencil {
-  int pn, ph, qn, qh;       // cell indices on node / half sub-grids
-  double frn, frh, ftn, fth;  // fractions
-};
-
-__device__ __forceinline__ void locate(const GridView& g, double r, double th,
-                                       Stencil& S) {
-  float lr = radial_coord(g, r);
-  double lt = (th - g.th0) * g.inv_dth;
-  int pn = refine(g.rn, g.nr + 1, r, (int)floorf(lr));
-  int ph = refine(g.rh, g.nr, r, (int)floorf(lr - 0.5f));
-  int qn = refine(g.tn, g.nth + 1, th, (int)floor(lt));
-  int qh = refine(g.th, g.nth, th, (int)floor(lt - 0.5));
-  S.pn = pn;
-  S.ph = ph;
-  S.qn = qn;
-  S.qh = qh;
-  S.frn = clamp01((r - g.rn[pn]) * g.idrn[pn]);
-  S.frh = clamp01((r - g.rh[ph]) * g.idrh[ph]);
-  S.ftn = clamp01((th - g.tn[qn]) * g.inv_dth);
-  S.fth = clamp01((th - g.th[qh]) * g.inv_dth);
+// theta nodes of the uniform grid, bit-identical to the host tables
+// (theta0 + j dth and theta0 + (j + 1/2) dth: rounded product, then sum)
+__device__ __forceinline__ double theta_node(const GridView& g, int j) {
+  return __dadd_rn(g.th0, __dmul_rn((double)j, g.dth));
+}
+__device__ __forceinline__ double theta_half(const GridView& g, int j) {
+  return __dadd_rn(g.th0, __dmul_rn((double)j + 0.5, g.dth));
 }
 
-__device__ __forceinline__ double bilin(const float* A, int nR, int p, int q,
-                                        double fr, double ft) {
-  const float* row0 = A + (long)q * nR + p;
-  const float* row1 = row0 + nR;
-  double v00 = row0[0], v10 = row0[1], v01 = row1[0], v11 = row1[1];
+// cell j in [0, n-2] of the n theta points (nodes, or half points if HALF)
+// with x_j <= th < x_{j+1} (clamped); lt = (th - theta0) / dth
+template <bool HALF>
+__device__ __forceinline__ int theta_cell(const GridView& g, double th, double lt, int n) {
+  int j = (int)floor(HALF ? lt - 0.5 : lt);
+  j = j < 0 ? 0 : (j > n - 2 ? n - 2 : j);
+  const double x0 = HALF ? theta_half(g, j) : theta_node(g, j);
+  const double x1 = HALF ? theta_half(g, j + 1) : theta_node(g, j + 1);
+  if (j > 0 && th < x0) --j;
+  else if (j < n - 2 && th >= x1) ++j;
+  return j;
+}
+
+
+// the two adjacent values of a row and of the next row of each component
+__device__ __forceinline__ float2 ld2(const float* p) { return make_float2(p[0], p[1]); }
+
+__device__ __forceinline__ void corner_loads(const FieldView& F, int nrn, int nrh, int pn,
+                                             int ph, int qn, int qh, float2* c) {
+  const float* a = F.Dr + (long)qn * nrh + ph;
+  c[0] = ld2(a);
+  c[1] = ld2(a + nrh);
+  a = F.Dt + (long)qh * nrn + pn;
+  c[2] = ld2(a);
+  c[3] = ld2(a + nrn);
+  a = F.Dp + (long)qn * nrn + pn;
+  c[4] = ld2(a);
+  c[5] = ld2(a + nrn);
+  a = F.Br + (long)qh * nrn + pn;
+  c[6] = ld2(a);
+  c[7] = ld2(a + nrn);
+  a = F.Bt + (long)qn * nrh + ph;
+  c[8] = ld2(a);
+  c[9] = ld2(a + nrh);
+  a = F.Bp + (long)qh * nrh + ph;
+  c[10] = ld2(a);
+  c[11] = ld2(a + nrh);
+}
+
+__device__ __forceinline__ double lerp2(float2 r0, float2 r1, double fr, double ft) {
+  double v00 = r0.x, v10 = r0.y, v01 = r1.x, v11 = r1.y;
   double b0 = v00 + fr * (v10 - v00);
   double b1 = v01 + fr * (v11 - v01);
   return b0 + ft * (b1 - b0);
 }
 
-// D^i, B^i at (r, theta): sum_c w_c (sqrt(g) F)_c / sqrt(g)(x)
+// D^i, B^i at (r, theta): sum_c w_c (sqrt(g) F)_c / sqrt(g)(x).  The theta
+// cells come from the uniform-grid formula; the radial cells from an FP32
+// estimate checked against the node tables.  The field corners of the
+// estimated cells are loaded together with those node values (one memory
+// round trip) and reloaded only when the estimate was one cell off.
 __device__ __forceinline__ void gather(const GridView& g, const FieldView& F,
                                        double r, double th, double isg,
                                        double* D, double* B) {
-  Stencil S;
-  locate(g, r, th, S);
-  int nrn = g.nr + 1, nrh = g.nr;
-  D[0] = bilin(F.Dr, nrh, S.ph, S.qn, S.frh, S.ftn) * isg;
-  D[1] = bilin(F.Dt, nrn, S.pn, S.qh, S.frn, S.fth) * isg;
-  D[2] = bilin(F.Dp, nrn, S.pn, S.qn, S.frn, S.ftn) * isg;
-  B[0] = bilin(F.Br, nrn, S.pn, S.qh, S.frn, S.fth) * isg;
-  B[1] = bilin(F.Bt, nrh, S.ph, S.qn, S.frh, S.ftn) * isg;
-  B[2] = bilin(F.Bp, nrh, S.ph, S.qh, S.frh, S.fth) * isg;
+  const int nr = g.nr, nrn = nr + 1, nrh = nr;
+  const double lt = (th - g.th0) * g.inv_dth;
+  const int qn = theta_cell<false>(g, th, lt, g.nth + 1);
+  const int qh = theta_cell<true>(g, th, lt, g.nth);
+  const float lr = radial_coord(g, r);
+  int pn = (int)floorf(lr), ph = (int)floorf(lr - 0.5f);
+  pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
+  ph = ph < 0 ? 0 : (ph > nr - 2 ? nr - 2 : ph);
+  float2 c[12];
+  corner_loads(F, nrn, nrh, pn, ph, qn, qh, c);
+  double rn0 = g.rn[pn], rn1 = g.rn[pn + 1], irn = g.idrn[pn];
+  double rh0 = g.rh[ph], rh1 = g.rh[ph + 1], irh = g.idrh[ph];
+  int pn2 = pn, ph2 = ph;
+  if (pn > 0 && r < rn0) --pn2;
+  else if (pn < nr - 1 && r >= rn1) ++pn2;
+  if (ph > 0 && r < rh0) --ph2;
+  else if (ph < nr - 2 && r >= rh1) ++ph2;
+  if (pn2 != pn || ph2 != ph) {
+    pn = pn2;
+    ph = ph2;
+    corner_loads(F, nrn, nrh, pn, ph, qn, qh, c);
+    rn0 = g.rn[pn];
+    irn = g.idrn[pn];
+    rh0 = g.rh[ph];
+    irh = g.idrh[ph];
+  }
+  const double frn = clamp01((r - rn0) * irn), frh = clamp01((r - rh0) * irh);
+  const double ftn = clamp01((th - theta_node(g, qn)) * g.inv_dth);
+  const double fth = clamp01((th - theta_half(g, qh)) * g.inv_dth);
+  D[0] = lerp2(c[0], c[1], frh, ftn) * isg;
+  D[1] = lerp2(c[2], c[3], frn, fth) * isg;
+  D[2] = lerp2(c[4], c[5], frn, ftn) * isg;
+  B[0] = lerp2(c[6], c[7], frn, fth) * isg;
+  B[1] = lerp2(c[8], c[9], frh, ftn) * isg;
+  B[2] = lerp2(c[10], c[11], frh, fth) * isg;
 }
 
 // ------------------------------------------------------- equations of motion
