@@ -39,11 +39,12 @@ __device__ __forceinline__ void sincos_steps(double s0, double c0, double h,
 
 // W[0..3] for nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1); st, ct = sin, cos
 // of th
-__device__ __forceinline__ void dep_weights(const GridView& g, double r,
-                                            double th, double st, double ct,
-                                            int p, int q, double* W) {
+// ra, rb: radii of the cell's node columns; sq, cq: sin, cos of its lower
+// node angle
+__device__ __forceinline__ void dep_weights_at(const GridView& g, double r, double th,
+                                               double st, double ct, double ra, double rb,
+                                               double sq, double cq, int q, double* W) {
   const double a2 = g.a * g.a;
-  double ra = g.rn[p], rb = g.rn[p + 1];
   double ta = theta_node(g, q), tb = theta_node(g, q + 1);
   double h1r = (r - ra) * (1.0 / 3.0), h2r = (rb - r) * (1.0 / 3.0);
   double h1t = (th - ta) * (1.0 / 3.0), h2t = (tb - th) * (1.0 / 3.0);
@@ -56,7 +57,7 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
   for (int i = 1; i < 4; ++i) R[3 + i] = r + i * h2r;
   {
     double Sa[4], Ca[4], Sb[4], Cb[4];
-    sincos_steps(g.stn[q], g.ctn[q], h1t, Sa, Ca);
+    sincos_steps(sq, cq, h1t, Sa, Ca);
     sincos_steps(st, ct, h2t, Sb, Cb);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -100,6 +101,36 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
   W[1] = Vab * iV;
   W[2] = Vba * iV;
   W[3] = Vaa * iV;
+}
+
+__device__ __forceinline__ void dep_weights(const GridView& g, double r,
+                                            double th, double st, double ct,
+                                            int p, int q, double* W) {
+  dep_weights_at(g, r, th, st, ct, g.rn[p], g.rn[p + 1], g.stn[q], g.ctn[q], q, W);
+}
+
+// node cell (p, q) of (r, th) and its weights, with the node values loaded in
+// one memory round trip (the FP32 radial estimate is checked against them)
+__device__ __forceinline__ void cell_and_weights(const GridView& g, double r, double th,
+                                                 double st, double ct, int& p, int& q,
+                                                 double* W) {
+  const int nr = g.nr;
+  q = theta_cell<false>(g, th, (th - g.th0) * g.inv_dth, g.nth + 1);
+  int p0 = (int)floorf(radial_coord(g, r));
+  p0 = p0 < 0 ? 0 : (p0 > nr - 1 ? nr - 1 : p0);
+  double r0 = g.rn[p0], r1 = g.rn[p0 + 1];
+  const double sq = g.stn[q], cq = g.ctn[q];
+  p = p0;
+  if (p0 > 0 && r < r0) {
+    p = p0 - 1;
+    r1 = r0;
+    r0 = g.rn[p];
+  } else if (p0 < nr - 1 && r >= r1) {
+    p = p0 + 1;
+    r0 = r1;
+    r1 = g.rn[p + 1];
+  }
+  dep_weights_at(g, r, th, st, ct, r0, r1, sq, cq, q, W);
 }
 
 __device__ __forceinline__ void dep_weights(const GridView& g, double r,

@@ -332,10 +332,9 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
     P.dphi[k] = out[2] - z[2];
     if (fl & F_ALIVE) {
       int p, q;
-      node_cell(A.g, out[0], out[1], p, q);
       double W[4], st, ct;
       sincos_near(out[1], z[1], s0, c0, &st, &ct);
-      dep_weights(A.g, out[0], out[1], st, ct, p, q, W);
+      cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W);
 #pragma unroll
       for (int c = 0; c < 4; ++c) P.Wn[c][k] = W[c];
       P.celln[k] = q * A.g.nr + p;
