@@ -22,10 +22,18 @@ struct DepArgs {
   ParticleView p;
   DepositAcc acc;
   int nr, nth;
+  double inv_nr;       // 1 / nr, to split a cell index without an integer division
   unsigned* fallback;  // blocks that used global atomics (diagnostic)
   int* xqueue;         // particles whose move crosses a node-cell boundary
   unsigned* xcount;
 };
+
+// node cell c = q nr + p -> (p, q); (c + 1/2) / nr in FP64 is exact enough to
+// floor correctly for any grid that fits in memory
+__device__ __forceinline__ void split_cell(const DepArgs& A, int c, int& p, int& q) {
+  q = (int)(((double)c + 0.5) * A.inv_nr);
+  p = c - q * A.nr;
+}
 
 // Where contributions go: the global accumulators, or a block's LDS bins
 // covering node columns [p0, p0 + bw) and rows [q0, q0 + bh).  The four
@@ -113,7 +121,9 @@ template <class Sink>
 __device__ bool deposit_particle(const DepArgs& A, const Sink& S, const PRec& d) {
   const double s = A.acc.scale;
   const double qw = d.qw;
-  const int p0 = d.c0 % A.nr, q0 = d.c0 / A.nr, p1 = d.c1 % A.nr, q1 = d.c1 / A.nr;
+  int p0, q0, p1, q1;
+  split_cell(A, d.c0, p0, q0);
+  split_cell(A, d.c1, p1, q1);
   const double hdphi = 0.5 * qw * d.dphi;
   const bool same = d.c0 == d.c1;
 #pragma unroll
@@ -211,10 +221,16 @@ __device__ __forceinline__ void segment_box(const DepArgs& A, long beg, long end
   }
   __syncthreads();
   int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
+  // unconditional loads, four particles at a time, so that they overlap
+#pragma unroll 4
   for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
-    if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) continue;
-    int c0 = P.cell[k], c1 = P.celln[k];
-    int p0 = c0 % A.nr, q0 = c0 / A.nr, p1 = c1 % A.nr, q1 = c1 / A.nr;
+    const uint8_t fl = P.flags[k];
+    const int8_t qm = P.qm[k];
+    const int c0 = P.cell[k], c1 = P.celln[k];
+    if (!(fl & GRPIC_FLAG_ALIVE) || qm == 0) continue;
+    int p0, q0, p1, q1;
+    split_cell(A, c0, p0, q0);
+    split_cell(A, c1, p1, q1);
     pmin = min(pmin, min(p0, p1));
     pmax = max(pmax, max(p0, p1));
     qmin = min(qmin, min(q0, q1));
@@ -287,7 +303,10 @@ __global__ __launch_bounds__(256) void k_deposit_crossing(DepArgs A) {
     long k = A.xqueue[i];
     int c0 = P.cell[k], c1 = P.celln[k];
     double qw = (double)P.qm[k] * P.w[k];
-    deposit_crossing(A, Gs, k, qw, c0 % A.nr, c0 / A.nr, c1 % A.nr, c1 / A.nr);
+    int p0, q0, p1, q1;
+    split_cell(A, c0, p0, q0);
+    split_cell(A, c1, p1, q1);
+    deposit_crossing(A, Gs, k, qw, p0, q0, p1, q1);
   }
 }
 
@@ -354,7 +373,8 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
   if (!(P.flags[k] & GRPIC_FLAG_ALIVE)) return;
   double qw = (double)P.qm[k] * P.w[k];
   int c0 = P.cell[k];
-  int p0 = c0 % A.nr, q0 = c0 / A.nr;
+  int p0, q0;
+  split_cell(A, c0, p0, q0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     long nn = (long)(q0 + (c >> 1)) * (A.nr + 1) + p0 + (c & 1);
@@ -438,6 +458,7 @@ void launch_deposit(grpic_ctx* c) {
     A.acc = c->acc;
     A.nr = c->nr;
     A.nth = c->nth;
+    A.inv_nr = 1.0 / c->nr;
     A.fallback = &c->stats->deposit_fallback;
     A.xqueue = c->xqueue;
     A.xcount = &c->stats->cross_count;
@@ -465,6 +486,7 @@ void launch_deposit_initial(grpic_ctx* c) {
     A.acc = c->acc;
     A.nr = c->nr;
     A.nth = c->nth;
+    A.inv_nr = 1.0 / c->nr;
     hipLaunchKernelGGL(k_deposit_rho, dim3(grid_for(c->n, 256)), dim3(256), 0,
                        c->stream, A);
     GRPIC_HIP(hipGetLastError());
