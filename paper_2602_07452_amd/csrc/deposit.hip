@@ -272,11 +272,13 @@ __device__ __forceinline__ void deposit_range(const DepArgs& A, long beg,
   const ParticleView& P = A.p;
   GlobalSink Gs{&A.acc, A.nr};
   const int lane = threadIdx.x & 63;
-  PRec cur, nxt;
+  // two particles ahead are in flight while one is accumulated
+  PRec cur, nxt, nxt2;
   load_rec(P, beg + threadIdx.x, end, cur);
+  load_rec(P, beg + kDepBlock + threadIdx.x, end, nxt);
   for (long kb = beg; kb < end; kb += kDepBlock) {  // uniform trip count
     const long k = kb + threadIdx.x;
-    load_rec(P, k + kDepBlock, end, nxt);  // prefetch the next particle
+    load_rec(P, k + 2 * kDepBlock, end, nxt2);
     bool cross = false;
     if (cur.act) {
       bool done = L ? deposit_particle(A, *L, cur) : deposit_particle(A, Gs, cur);
@@ -289,6 +291,7 @@ __device__ __forceinline__ void deposit_range(const DepArgs& A, long beg,
       X.n += __popcll(m);
     }
     cur = nxt;
+    nxt = nxt2;
   }
 }
 
