@@ -353,9 +353,10 @@ void advance_host_state(grpic_ctx* c) {
 }
 
 void drop_graphs(grpic_ctx* c) {
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  c->graph_exec = nullptr;
-  c->graph_parity = -1;
+  for (auto& g : c->graph_exec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
 }
 
 void run_step(grpic_ctx* c) {
@@ -363,9 +364,8 @@ void run_step(grpic_ctx* c) {
     step_kernels(c);
     advance_host_state(c);
   } else {
-    int parity = (int)(c->steps & 1);
-    if (c->graph_exec == nullptr || c->graph_parity != parity) {
-      drop_graphs(c);
+    const int key = (int)(c->steps & 1) + 2 * c->sort_flip;
+    if (c->graph_exec[key] == nullptr) {
       bool was_timing = c->timing;
       c->timing = false;
       hipGraph_t g = nullptr;
@@ -380,23 +380,16 @@ void run_step(grpic_ctx* c) {
       }
       GRPIC_HIP(hipStreamEndCapture(c->stream, &g));
       c->timing = was_timing;
-      GRPIC_HIP(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-      GRPIC_HIP(hipGraphDestroy(g));
-      c->graph_parity = parity;
-      GRPIC_HIP(hipGraphLaunch(c->graph_exec, c->stream));
-      advance_host_state(c);
-      // the captured graph is valid for this parity only; replays of the
-      // other parity capture their own graph
-      return;
+      hipError_t e = hipGraphInstantiate(&c->graph_exec[key], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      GRPIC_HIP(e);
     }
-    GRPIC_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    GRPIC_HIP(hipGraphLaunch(c->graph_exec[key], c->stream));
     advance_host_state(c);
   }
   if (c->cfg.sort_every > 0 && c->cfg.field_mode != GRPIC_FIELDS_NONE &&
-      c->steps % c->cfg.sort_every == 0) {
-    launch_sort(c);
-    drop_graphs(c);
-  }
+      c->steps % c->cfg.sort_every == 0)
+    launch_sort(c);  // swaps the buffer sets: the other cached graphs apply
 }
 
 hipEvent_t take_event(grpic_ctx* c) {

@@ -126,8 +126,11 @@ struct grpic_ctx {
   void* mlp = nullptr;
   // graph
   bool use_graph = false;
-  hipGraphExec_t graph_exec = nullptr;
-  int graph_parity = -1;
+  // captured steps, one per (step parity, particle buffer set): the step
+  // alternates its level pointers every step and the sort swaps the two
+  // particle buffer sets
+  hipGraphExec_t graph_exec[4]{};
+  int sort_flip = 0;
   // timing
   bool timing = false;
   double t_ms[GRPIC_K_COUNT]{};

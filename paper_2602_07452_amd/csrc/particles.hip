@@ -309,6 +309,7 @@ void launch_sort(grpic_ctx* c) {
   GRPIC_HIP(hipGetLastError());
   ParticleView& P = c->pv;
   ParticleView& Q = c->alt;
+  c->sort_flip ^= 1;
   std::swap(P.r, Q.r);
   std::swap(P.th, Q.th);
   std::swap(P.ph, Q.ph);
