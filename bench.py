@@ -118,7 +118,7 @@ WORKLOADS = {
 }
 
 
-def make_context(G, W, n=None, push_wps=0):
+def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
     a = W["a"]
     rp = rplus(a)
     evolve = W["mode"] == "evolve"
@@ -132,6 +132,8 @@ def make_context(G, W, n=None, push_wps=0):
         guess=G.GUESS_MLP if W.get("guess") == "mlp" else G.GUESS_RK4,
         sort_every=W.get("sort_every", 50),
         push_waves_per_simd=push_wps)
+    if persistent_waves:
+        cfg.persistent_waves = persistent_waves
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
     ctx = G.Context(cfg)
     if W.get("fields") == "monopole":
@@ -299,6 +301,8 @@ def main():
     ap.add_argument("--particles", type=int, default=0, help="override particle count")
     ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
     ap.add_argument("--push-wps", type=int, default=0, help="explicit-push waves per SIMD")
+    ap.add_argument("--persistent-waves", type=int, default=0,
+                    help="implicit-pass waves per CU (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -322,7 +326,8 @@ def main():
     W = dict(WORKLOADS[args.workload])
     if args.particles:
         W["n"] = args.particles
-    ctx, cfg = make_context(G, W, push_wps=args.push_wps)
+    ctx, cfg = make_context(G, W, push_wps=args.push_wps,
+                            persistent_waves=args.persistent_waves)
     print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,
           flush=True)
     graph = bool(args.graph or W.get("graph", 0))
