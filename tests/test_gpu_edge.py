@@ -1,0 +1,183 @@
+"""Edge and degenerate cases of the GPU path against the oracle: particles
+exactly on grid nodes, half points and the theta edges; an empty particle
+set; neutral and charged particles together in grid fields (the
+discrete-gradient implicit pass with a grid); the non-rotating hole a = 0."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2602_07452_amd as G
+from gpu_common import (TOL_FIELD, TOL_STATE, compare_push, gpu_fields_as_G, norm_err,
+                        oracle_grid, oracle_particles, push_params_from, rplus)
+
+pytestmark = pytest.mark.gpu
+
+SEED = 2602074520
+
+
+def _pic_cfg(a=0.99, n=2048, nr=40, nth=32):
+    cfg = G.config_default(a=a, nr=nr, nth=nth, r_in=0.9 * rplus(a), r_out=20.0,
+                           field_mode=G.FIELDS_EVOLVE, pusher=G.PUSH_HYB2,
+                           hyb_threshold=1e-9, max_particles=n, r_remove_in=rplus(a),
+                           r_remove_out=20.0, reflect=1, r_abs=18.0, chi0=1e4,
+                           lambda_abs=5.0, tile_r=16, tile_th=16)
+    cfg.dt = 0.5 * G.cfl_dt(cfg)
+    return cfg
+
+
+def _levels(ctx):
+    return {lev: [ctx.get_field(lev, c) for c in range(4 if lev >= G.LEVEL_J else 3)]
+            for lev in range(8)}
+
+
+def _oracle_fields(g, S):
+    F = O.Fields(g)
+    dd = lambda lev, off: [g.densitize(off + c, S[lev][c].astype(np.float64), -1)
+                           for c in range(3)]
+    F.Dn, F.Dh0, F.Dh1 = dd(G.LEVEL_DN, 0), dd(G.LEVEL_DH0, 0), dd(G.LEVEL_DH1, 0)
+    F.Bm, F.Bn, F.Bh = dd(G.LEVEL_BM, 3), dd(G.LEVEL_BN, 3), dd(G.LEVEL_BH, 3)
+    F.Jprev = [S[G.LEVEL_J][c].astype(np.float64) for c in range(3)]
+    F.rho = S[G.LEVEL_J][3].astype(np.float64)
+    return F
+
+
+def _field_errors(g, F, S1):
+    errs = {}
+    for name, lev, arrs, off in (("Dn", G.LEVEL_DN, F.Dn, 0), ("Dh0", G.LEVEL_DH0, F.Dh0, 0),
+                                 ("Dh1", G.LEVEL_DH1, F.Dh1, 0), ("Bm", G.LEVEL_BM, F.Bm, 3),
+                                 ("Bn", G.LEVEL_BN, F.Bn, 3), ("Bh", G.LEVEL_BH, F.Bh, 3)):
+        for c in range(3):
+            errs[f"{name}{c}"] = norm_err(S1[lev][c], g.densitize(off + c, arrs[c]))
+    return {k: v for k, v in errs.items() if not v <= TOL_FIELD}
+
+
+def _grid_point_particles(ctx, cfg):
+    """e+/e- pairs placed exactly on nodes, half points, the theta edges and
+    one ulp below nodes, with small random momenta."""
+    rn, rh, tn, th = ctx.grid_coords()
+    rng = np.random.default_rng(SEED + 30)
+    inside = lambda r: r > rplus(cfg.a) * 1.05 and r < 17.0
+    pts = []
+    for i in range(2, cfg.nr - 2, 3):
+        for j in range(0, cfg.nth + 1, 4):
+            for r, t in ((rn[i], tn[j]), (rh[i], tn[j]), (rn[i], th[min(j, cfg.nth - 1)]),
+                         (np.nextafter(rn[i], 0.0), tn[j]), (rn[i], np.nextafter(tn[j], 0.0))):
+                if inside(r) and cfg.theta0 <= t <= np.pi - cfg.theta0:
+                    pts.append((r, t))
+    pts = np.array(pts[: cfg.max_particles // 2])
+    m = len(pts)
+    z = np.zeros((2 * m, 6))
+    z[0::2, 0] = z[1::2, 0] = pts[:, 0]
+    z[0::2, 1] = z[1::2, 1] = pts[:, 1]
+    z[:, 2] = rng.uniform(0, 2 * np.pi, 2 * m)
+    z[:, 3:] = rng.normal(0, 0.05, (2 * m, 3))
+    qm = np.tile([1.0, -1.0], m)
+    return z, qm
+
+
+def test_particles_on_nodes_and_edges():
+    cfg = _pic_cfg()
+    g = oracle_grid(cfg)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        z, qm = _grid_point_particles(ctx, cfg)
+        ctx.load_particles(z, qm, w=np.full(len(qm), 1e-3))
+        S0 = _levels(ctx)
+        P0 = ctx.get_particles()
+        ctx.step(1)
+        S1 = _levels(ctx)
+        P1 = ctx.get_particles()
+    assert len(qm) > 100
+    # initial charge of co-located pairs cancels exactly
+    assert np.abs(S0[G.LEVEL_J][3]).max() == 0.0
+    G6 = [S0[G.LEVEL_DH1][c].astype(np.float64) for c in range(3)] + \
+         [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
+    err, _ = compare_push(cfg, P0, P1, push_params_from(cfg, O.FIELDS_GRID), grid=g, G6=G6)
+    assert err <= TOL_STATE
+    alive = ((P0["flags"] & 1) != 0) & ((P1["flags"] & 1) != 0)
+    old = np.stack([P0["r"], P0["th"], P0["ph"]], axis=1)
+    new = np.stack([P1["r"], P1["th"], P1["ph"]], axis=1)
+    rho, Jr, Jt, Jp = O.deposit(g, cfg.dt, old, new, P0["qm"] * P0["w"], alive.astype(np.int32))
+    for got, want in ((S1[G.LEVEL_J][3], rho), (S1[G.LEVEL_J][0], Jr),
+                      (S1[G.LEVEL_J][1], Jt), (S1[G.LEVEL_J][2], Jp)):
+        assert norm_err(got, want) < 1e-6
+    # and the field update around them
+    F = _oracle_fields(g, S0)
+    O.pic_step(push_params_from(cfg, O.FIELDS_GRID), g, F, oracle_particles(P0),
+               absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
+    assert not _field_errors(g, F, S1)
+
+
+def test_empty_particle_set_evolves_vacuum_fields():
+    cfg = _pic_cfg(n=64)
+    g = oracle_grid(cfg)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        assert ctx.num_particles() == 0
+        S0 = _levels(ctx)
+        ctx.step(1)
+        S1 = _levels(ctx)
+        d = ctx.diagnostics()
+    assert d["alive"] == 0 and d["implicit_steps"] == 0
+    assert all(np.abs(S1[G.LEVEL_J][c]).max() == 0.0 for c in range(4))
+    F = _oracle_fields(g, S0)
+    O.pic_step(push_params_from(cfg, O.FIELDS_GRID), g, F, None,
+               absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
+    assert not _field_errors(g, F, S1)
+
+
+def test_neutral_and_charged_particles_in_grid_fields():
+    """Hyb2 with neutral particles among charged ones in the static Wald grid
+    field: neutral rejects go to the discrete-gradient scheme, charged ones
+    to the implicit midpoint rule, in one implicit pass."""
+    a = 0.9
+    n = 3000
+    cfg = G.config_default(a=a, nr=64, nth=48, r_in=0.9 * rplus(a), r_out=50.0, dt=0.05,
+                           field_mode=G.FIELDS_STATIC, pusher=G.PUSH_HYB2,
+                           hyb_threshold=1e-12, max_particles=n, r_remove_in=rplus(a),
+                           r_remove_out=50.0, reflect=1, guess=G.GUESS_RK4)
+    g = oracle_grid(cfg)
+    p = O.init_particles(O.INIT_SHELL_ISO, a, SEED + 31, n, 2.0, 30.0, cfg.theta0,
+                         np.pi - cfg.theta0, 1.0)
+    qm = p.qm.copy()
+    qm[::3] = 0.0
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.load_particles(p.state(), qm)
+        G6 = gpu_fields_as_G(ctx)
+        ctx.step(1)
+        before = ctx.get_particles()
+        ctx.step(1)
+        after = ctx.get_particles()
+    err, _ = compare_push(cfg, before, after, push_params_from(cfg, O.FIELDS_GRID),
+                          grid=g, G6=G6)
+    assert err <= TOL_STATE
+    impl = (after["flags"] & G.FLAG_IMPLICIT) != 0
+    neutral = before["qm"] == 0
+    assert impl[neutral].any() and impl[~neutral].any()
+    assert (~impl[neutral]).any() and (~impl[~neutral]).any()
+
+
+def test_schwarzschild_full_step():
+    """a = 0: the Wald field reduces to a uniform field in Schwarzschild
+    (App. B.1); one full cycle matches the oracle."""
+    cfg = _pic_cfg(a=0.0, n=3000)
+    g = oracle_grid(cfg)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 32, rplus(0.0), 18.0,
+                           cfg.theta0, np.pi - cfg.theta0, 0.1, w=2e-3)
+        ctx.step(2)
+        S0 = _levels(ctx)
+        P0 = ctx.get_particles()
+        ctx.step(1)
+        S1 = _levels(ctx)
+        P1 = ctx.get_particles()
+    F = _oracle_fields(g, S0)
+    O.pic_step(push_params_from(cfg, O.FIELDS_GRID), g, F, oracle_particles(P0),
+               absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
+    assert not _field_errors(g, F, S1)
+    G6 = [S0[G.LEVEL_DH1][c].astype(np.float64) for c in range(3)] + \
+         [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
+    err, _ = compare_push(cfg, P0, P1, push_params_from(cfg, O.FIELDS_GRID), grid=g, G6=G6)
+    assert err <= TOL_STATE
