@@ -42,6 +42,10 @@ FLOP_IMR_ITER = FLOP_EVAL + FLOP_IMR_EXTRA
 BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 32 + 4
 # deposit per particle: old/new weights and cells, q/m, w, dphi, flags
 BYTES_DEPOSIT = 32 + 32 + 4 + 4 + 1 + 8 + 8 + 1
+# one launch of the Maxwell group (sub-steps 1-4, or 7-10) per cell: about 65
+# FP32 arrays read or written (two constitutive updates with their metric
+# coefficient tables and two curl updates)
+BYTES_FIELDS_PER_CELL = 65 * 4
 
 
 # Kernel per timing group, as named in rocprofv3 traces, and the source files
@@ -394,6 +398,26 @@ def main():
                     "traffic": counter_traffic(dom, args.workload, W["n"]),
                     "avg_launch_ms": avg_s * 1e3}
         roof["algorithmic_bytes"] = BYTES_PUSH * n_alive if dom == "push" else None
+        # every timing group against its own bound (per launch)
+        groups = {}
+        for grp in ("push", "implicit", "deposit", "fields"):
+            cnt_g = tim.get(grp, (0.0, 0))[1]
+            if cnt_g == 0:
+                continue
+            avg_g = tim[grp][0] / cnt_g * 1e-3
+            if grp in ("push", "implicit"):
+                a_g = flops[grp] / cnt_g / avg_g / 1e12
+                groups[grp] = {"bound": "alu", "achieved": a_g, "peak": PEAK_FP64_TFLOPS,
+                               "unit": "TFLOP/s", "frac": a_g / PEAK_FP64_TFLOPS}
+            else:
+                nb = (BYTES_DEPOSIT * n_alive if grp == "deposit"
+                      else BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"])
+                a_g = nb / avg_g / 1e9
+                groups[grp] = {"bound": "hbm", "achieved": a_g, "peak": PEAK_HBM_GBS,
+                               "unit": "GB/s", "frac": a_g / PEAK_HBM_GBS}
+            groups[grp]["avg_launch_ms"] = avg_g * 1e3
+            groups[grp]["traffic"] = counter_traffic(grp, args.workload, W["n"])
+        roof["groups"] = groups
         roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
                                       if v[1] > 0}
 
