@@ -38,10 +38,11 @@ FLOP_SWITCH = 2 * FLOP_ENERGY + 4
 FLOP_IMR_ITER = FLOP_EVAL + FLOP_IMR_EXTRA
 # algorithmic HBM bytes per particle of the explicit push pass: state in/out
 # (2 x 48), q/m, flags, H0, herr in/out, iterations, old position + dphi,
-# new weights + cell
-BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 32 + 4
-# deposit per particle: old/new weights and cells, q/m, w, dphi, flags
-BYTES_DEPOSIT = 32 + 32 + 4 + 4 + 1 + 8 + 8 + 1
+# new weights (three stored, the fourth is their complement) + cell
+BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 24 + 4
+# deposit per particle: old/new weights (three each) and cells, q/m, w, dphi,
+# flags
+BYTES_DEPOSIT = 24 + 24 + 4 + 4 + 1 + 8 + 8 + 1
 # one launch of the Maxwell group (sub-steps 1-4, or 7-10) per cell: about 65
 # FP32 arrays read or written (two constitutive updates with their metric
 # coefficient tables and two curl updates)
@@ -305,6 +306,8 @@ def main():
     ap.add_argument("--particles", type=int, default=0, help="override particle count")
     ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
     ap.add_argument("--push-wps", type=int, default=0, help="explicit-push waves per SIMD")
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="steps between particle re-sorts (0: the workload's value)")
     ap.add_argument("--persistent-waves", type=int, default=0,
                     help="implicit-pass waves per CU (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -330,6 +333,8 @@ def main():
     W = dict(WORKLOADS[args.workload])
     if args.particles:
         W["n"] = args.particles
+    if args.sort_every:
+        W["sort_every"] = args.sort_every
     ctx, cfg = make_context(G, W, push_wps=args.push_wps,
                             persistent_waves=args.persistent_waves)
     print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,

@@ -112,11 +112,12 @@ void alloc_particles(grpic_ctx* c, long cap) {
     V->iters = dalloc<uint8_t>(n);
     V->id = dalloc<uint32_t>(n);
     bool grid = c->cfg.field_mode != GRPIC_FIELDS_NONE;
-    for (int q = 0; q < 4; ++q) V->W[q] = grid ? dalloc<double>(n) : nullptr;
+    // weights of nodes 1..3; node 0's is the complement 1 - W1 - W2 - W3
+    for (int q = 1; q < 4; ++q) V->W[q] = grid ? dalloc<double>(n) : nullptr;
     V->cell = grid ? dalloc<int>(n) : nullptr;
   }
   bool evolve = c->cfg.field_mode == GRPIC_FIELDS_EVOLVE;
-  for (int q = 0; q < 4; ++q) P.Wn[q] = evolve ? dalloc<double>(n) : nullptr;
+  for (int q = 1; q < 4; ++q) P.Wn[q] = evolve ? dalloc<double>(n) : nullptr;
   P.celln = evolve ? dalloc<int>(n) : nullptr;
   P.r_old = evolve ? dalloc<double>(n) : nullptr;
   P.th_old = evolve ? dalloc<double>(n) : nullptr;

@@ -105,10 +105,12 @@ __device__ __forceinline__ void load_rec(const ParticleView& P, long k, long end
   d.c0 = P.cell[k];
   d.c1 = P.celln[k];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 1; c < 4; ++c) {
     d.Wo[c] = P.W[c][k];
     d.Wn[c] = P.Wn[c][k];
   }
+  d.Wo[0] = 1.0 - d.Wo[1] - d.Wo[2] - d.Wo[3];
+  d.Wn[0] = 1.0 - d.Wn[1] - d.Wn[2] - d.Wn[3];
   d.dphi = P.dphi[k];
   d.qw = (double)qm * w;
   d.act = (fl & GRPIC_FLAG_ALIVE) && d.qw != 0.0;
@@ -152,10 +154,12 @@ __device__ void deposit_crossing(const DepArgs& A, const Sink& S, long k,
   const ParticleView& P = A.p;
   double Wo[4], Wn[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 1; c < 4; ++c) {
     Wo[c] = P.W[c][k];
     Wn[c] = P.Wn[c][k];
   }
+  Wo[0] = 1.0 - Wo[1] - Wo[2] - Wo[3];
+  Wn[0] = 1.0 - Wn[1] - Wn[2] - Wn[3];
   const double s = A.acc.scale;
   const double r0 = P.r_old[k], t0 = P.th_old[k], r1 = P.r[k], t1 = P.th[k];
   int cp = p0, cq = q0;
@@ -381,7 +385,8 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     long nn = (long)(q0 + (c >> 1)) * (A.nr + 1) + p0 + (c & 1);
-    long long q = llrint(qw * P.W[c][k] * A.acc.scale);
+    const double wc = c ? P.W[c][k] : 1.0 - P.W[1][k] - P.W[2][k] - P.W[3][k];
+    long long q = llrint(qw * wc * A.acc.scale);
     if (q != 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(A.acc.Q + nn),
                 static_cast<unsigned long long>(q));
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(256) void k_weights(GridView g, ParticleView P) {
   double W[4];
   dep_weights(g, r, th, p, q, W);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) P.W[c][k] = W[c];
+  for (int c = 1; c < 4; ++c) P.W[c][k] = W[c];
   P.cell[k] = q * g.nr + p;
 }
 

@@ -23,9 +23,11 @@ struct ParticleView {
   int8_t* qm;                            // q/m in {+1, -1, 0}
   uint8_t *flags, *iters;
   uint32_t* id;
-  double* W[4];                          // deposit weights at x (current)
+  // deposit weights of the cell's nodes 1..3 at x (W[0] unused: node 0's
+  // weight is 1 - W1 - W2 - W3, so the four sum to one to FP64 rounding)
+  double* W[4];
   int* cell;                             // node cell index q * nr + p
-  double* Wn[4];                         // weights at the pushed position
+  double* Wn[4];                         // the same at the pushed position
   int* celln;
   double *r_old, *th_old, *dphi;         // previous position, phi change
 };

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
     D.iters[d] = S.iters[k];
     D.id[d] = S.id[k];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) D.W[c][d] = S.W[c][k];
+    for (int c = 1; c < 4; ++c) D.W[c][d] = S.W[c][k];
     D.cell[d] = S.cell[k];
   }
 }
@@ -323,7 +323,7 @@ void launch_sort(grpic_ctx* c) {
   std::swap(P.flags, Q.flags);
   std::swap(P.iters, Q.iters);
   std::swap(P.id, Q.id);
-  for (int q = 0; q < 4; ++q) std::swap(P.W[q], Q.W[q]);
+  for (int q = 1; q < 4; ++q) std::swap(P.W[q], Q.W[q]);
   std::swap(P.cell, Q.cell);
   time_end(c, GRPIC_K_SORT, ev);
 }

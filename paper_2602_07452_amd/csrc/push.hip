@@ -336,7 +336,7 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
       sincos_near(out[1], z[1], s0, c0, &st, &ct);
       cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) P.Wn[c][k] = W[c];
+      for (int c = 1; c < 4; ++c) P.Wn[c][k] = W[c];
       P.celln[k] = q * A.g.nr + p;
     }
   }
