@@ -114,6 +114,12 @@ WORKLOADS = {
               "hipGraph"),
         a=0.9, nr=2048, nth=2048, r_out=100.0, n=1 << 27, mode="evolve", fields="monopole",
         pusher="hyb2", thr=1e-13, theta=0.05, r_abs=90.0, graph=1, guess="mlp"),
+    "c1": dict(
+        desc=("neutral test particles in Schwarzschild (a=0), no fields: 1024 particles, "
+              "r in [6, 20], theta in [pi/4, 3pi/4], even ids circular, odd ids eccentric, "
+              "dt=0.01, Hyb2 (RK4 -> Hamiltonian discrete gradient) at 1e-15"),
+        a=0.0, nr=0, nth=0, r_out=1e9, n=1024, mode="none", pusher="hyb2", thr=1e-15,
+        dt=0.01, theta=0.1),
     "c2": dict(
         desc=("charged test particles in the Kerr a=0.9 Wald field (B0=1) on a "
               "512x512 grid, r in [0.9 r+, 50]: 2^20 particles, q/m=+-1, |u|~U[0,1] "
@@ -128,6 +134,14 @@ def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
     rp = rplus(a)
     evolve = W["mode"] == "evolve"
     n = W["n"] if n is None else n
+    if W["mode"] == "none":
+        # test particles without fields (circular and eccentric orbits)
+        cfg = G.config_default(a=a, dt=W["dt"], pusher=G.PUSH_HYB2, hyb_threshold=W["thr"],
+                               max_particles=n, r_remove_in=rp, guess=G.GUESS_RK4)
+        ctx = G.Context(cfg)
+        ctx.init_particles(G.INIT_ORBITS, n, SEED + 1, 6.0, 20.0, np.pi / 4, 3 * np.pi / 4,
+                           W["theta"])
+        return ctx, cfg
     cfg = G.config_default(
         a=a, nr=W["nr"], nth=W["nth"], r_in=0.9 * rp, r_out=W["r_out"],
         field_mode=G.FIELDS_EVOLVE if evolve else G.FIELDS_STATIC,
@@ -176,6 +190,20 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
     workload's particle count."""
     import oracle as O
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if W["mode"] == "none":
+        p = O.init_particles(O.INIT_ORBITS, cfg.a, SEED + 1, W["n"], 6.0, 20.0, np.pi / 4,
+                             3 * np.pi / 4, W["theta"])
+        P = O.push_params(cfg.a, cfg.dt, pusher=O.HYB2, guess=O.GUESS_RK4,
+                          thr=cfg.hyb_threshold, tol=cfg.tol, kmax=cfg.kmax,
+                          field_kind=O.FIELDS_NONE, r_min=cfg.r_remove_in, r_max=1e30,
+                          th_lo=-1.0, th_hi=10.0)
+        t0 = time.perf_counter()
+        for _ in range(sample_steps):
+            O.push(P, p)
+        t = time.perf_counter() - t0
+        return {"value": W["n"] * sample_steps / t, "unit": "particle-steps/s",
+                "cores": nthreads, "kind": "oracle",
+                "sample": f"all {W['n']} particles x {sample_steps} steps"}
     g = O.Grid(cfg.a, cfg.nr, cfg.nth, cfg.r_in, cfg.r_out, cfg.theta0)
     if W.get("fields") == "monopole":
         D, B = O.split_monopole_grid(g, 1.0, 1e3)
@@ -377,10 +405,13 @@ def main():
     impl = d1["implicit_steps"] - d0["implicit_steps"]
     iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
     evolve = W["mode"] == "evolve"
+    grid = W["mode"] != "none"
+    flop_rk4 = FLOP_RK4 if grid else FLOP_RK4 - 4 * FLOP_GATHER
+    flop_iter = FLOP_IMR_ITER if grid else FLOP_IMR_ITER - FLOP_GATHER
     flops = {
-        "push": args.steps * n_alive * (FLOP_RK4 + FLOP_SWITCH) +
+        "push": args.steps * n_alive * (flop_rk4 + FLOP_SWITCH) +
         (args.steps * n_alive - impl) * (FLOP_WEIGHTS if evolve else 0),
-        "implicit": iters * FLOP_IMR_ITER + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
+        "implicit": iters * flop_iter + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
     }
     roof = None
     if not graph:
@@ -444,9 +475,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": W["desc"], "particles": W["n"], "grid": [W["nr"], W["nth"]],
-                   "dt": cfg.dt, "pusher": "Hyb2 (RK4 -> IMR)", "threshold": cfg.hyb_threshold,
+                   "dt": cfg.dt,
+                   "pusher": ("Hyb2 (RK4 -> IMR)" if grid
+                              else "Hyb2 (RK4 -> Hamiltonian discrete gradient)"),
+                   "threshold": cfg.hyb_threshold,
                    "guess": ("RK4 result + learned correction" if mlp_info else "RK4 result"),
-                   "fields": "FP32", "particle_state": "FP64",
+                   "fields": "FP32" if grid else "none", "particle_state": "FP64",
                    "graph": graph, "sort_every": cfg.sort_every,
                    "tile": [cfg.tile_r, cfg.tile_th]},
         "implicit_fraction": impl / max(args.steps * n_alive, 1),
