@@ -78,3 +78,40 @@ def test_full_size_plasma_wald():
 def test_full_size_split_monopole_learned_graph():
     """2^27 particles on 2048^2 with the learned guess and graph replay."""
     _check_full_size("c5", learned=True)
+
+
+def test_full_size_charged_test_particles():
+    """2^20 charged test particles in the static Wald grid field (Hyb2 with the
+    RK4 result as first iterate), sampled."""
+    W = dict(bench.WORKLOADS["c2"])
+    ctx, cfg = bench.make_context(G, W)
+    try:
+        G6 = [ctx.get_field(G.LEVEL_DH1, c).astype(np.float64) for c in range(3)] + \
+             [ctx.get_field(G.LEVEL_BH, c).astype(np.float64) for c in range(3)]
+        ctx.step(3)
+        rng = np.random.default_rng(2602074520 + 18)
+        ids = np.sort(rng.choice(ctx.num_particles(), NSAMPLE, replace=False))
+        before = ctx.sample_particles(ids)
+        ctx.step(1)
+        after = ctx.sample_particles(ids)
+    finally:
+        ctx.close()
+    err, _ = compare_push(cfg, before, after, push_params_from(cfg, O.FIELDS_GRID),
+                          grid=oracle_grid(cfg), G6=G6)
+    assert err <= TOL_STATE
+
+
+def test_full_size_neutral_test_particles():
+    """All 1024 neutral particles of the Schwarzschild test-particle workload,
+    one Hyb2 step (RK4 -> discrete gradient) after 20."""
+    W = dict(bench.WORKLOADS["c1"])
+    ctx, cfg = bench.make_context(G, W)
+    try:
+        ctx.step(20)
+        before = ctx.get_particles()
+        ctx.step(1)
+        after = ctx.get_particles()
+    finally:
+        ctx.close()
+    err, _ = compare_push(cfg, before, after, push_params_from(cfg, O.FIELDS_NONE))
+    assert err <= TOL_STATE
