@@ -48,49 +48,51 @@ __device__ __forceinline__ void dep_weights_at(const GridView& g, double r, doub
   double ta = theta_node(g, q), tb = theta_node(g, q + 1);
   double h1r = (r - ra) * (1.0 / 3.0), h2r = (rb - r) * (1.0 / 3.0);
   double h1t = (th - ta) * (1.0 / 3.0), h2t = (tb - th) * (1.0 / 3.0);
-  // 7 radii: ra + i h1r (i = 0..2), r, r + i h2r (i = 1..3); same for theta
-  double R[7], S[7], C2[7];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) R[i] = ra + i * h1r;
-  R[3] = r;
-#pragma unroll
-  for (int i = 1; i < 4; ++i) R[3 + i] = r + i * h2r;
-  {
-    double Sa[4], Ca[4], Sb[4], Cb[4];
-    sincos_steps(sq, cq, h1t, Sa, Ca);
-    sincos_steps(st, ct, h2t, Sb, Cb);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      S[j] = fabs(Sa[j]);
-      C2[j] = a2 * Ca[j] * Ca[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      S[3 + j] = fabs(Sb[j]);
-      C2[3 + j] = a2 * Cb[j] * Cb[j];
-    }
-  }
+  // 7 radii ra + i h1r (i = 0..2), r, r + i h2r (i = 1..3), and 7 angles the
+  // same way; the rows are visited in order and their angles advanced by the
+  // angle-addition recurrence of sincos_steps (few values live at a time)
+  const double h1t2 = h1t * h1t, h2t2 = h2t * h2t;
+  const double sh1 = h1t * (1.0 - h1t2 * (1.0 / 6.0) * (1.0 - h1t2 * (1.0 / 20.0) *
+                     (1.0 - h1t2 * (1.0 / 42.0) * (1.0 - h1t2 * (1.0 / 72.0)))));
+  const double ch1 = 1.0 - h1t2 * 0.5 * (1.0 - h1t2 * (1.0 / 12.0) *
+                     (1.0 - h1t2 * (1.0 / 30.0) * (1.0 - h1t2 * (1.0 / 56.0))));
+  const double sh2 = h2t * (1.0 - h2t2 * (1.0 / 6.0) * (1.0 - h2t2 * (1.0 / 20.0) *
+                     (1.0 - h2t2 * (1.0 / 42.0) * (1.0 - h2t2 * (1.0 / 72.0)))));
+  const double ch2 = 1.0 - h2t2 * 0.5 * (1.0 - h2t2 * (1.0 / 12.0) *
+                     (1.0 - h2t2 * (1.0 / 30.0) * (1.0 - h2t2 * (1.0 / 56.0))));
   // trapezoid weights along each half: (1/2, 1, 1, 1/2)
   double Vaa = 0.0, Vba = 0.0, Vab = 0.0, Vbb = 0.0;
-#pragma unroll
+  double Sj = sq, Cj = cq;
+#pragma unroll 1
   for (int j = 0; j < 7; ++j) {
+    if (j == 3) {
+      Sj = st;
+      Cj = ct;
+    }
+    const double Sabs = fabs(Sj), C2 = a2 * Cj * Cj;
     double wa_t = (j == 0 || j == 3) ? 0.5 : (j < 3 ? 1.0 : 0.0);
     double wb_t = (j == 3 || j == 6) ? 0.5 : (j > 3 ? 1.0 : 0.0);
     double rowa = 0.0, rowb = 0.0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-      double rr = R[i];
-      double rho2 = rr * rr + C2[j];
+      const double rr = i < 3 ? ra + i * h1r : (i == 3 ? r : r + (i - 3) * h2r);
+      double rho2 = rr * rr + C2;
       double f = fsqrt(rho2 * (rho2 + 2.0 * rr));
       double wa_r = (i == 0 || i == 3) ? 0.5 : (i < 3 ? 1.0 : 0.0);
       double wb_r = (i == 3 || i == 6) ? 0.5 : (i > 3 ? 1.0 : 0.0);
       rowa += wa_r * f;
       rowb += wb_r * f;
     }
-    Vaa += wa_t * S[j] * rowa;  // [ra, r] x [ta, th]
-    Vba += wa_t * S[j] * rowb;  // [r, rb] x [ta, th]
-    Vab += wb_t * S[j] * rowa;  // [ra, r] x [th, tb]
-    Vbb += wb_t * S[j] * rowb;  // [r, rb] x [th, tb]
+    Vaa += wa_t * Sabs * rowa;  // [ra, r] x [ta, th]
+    Vba += wa_t * Sabs * rowb;  // [r, rb] x [ta, th]
+    Vab += wb_t * Sabs * rowa;  // [ra, r] x [th, tb]
+    Vbb += wb_t * Sabs * rowb;  // [r, rb] x [th, tb]
+    if (j < 2 || (j >= 3 && j < 6)) {
+      const double ch = j < 3 ? ch1 : ch2, sh = j < 3 ? sh1 : sh2;
+      const double Sn = Sj * ch + Cj * sh;
+      Cj = Cj * ch - Sj * sh;
+      Sj = Sn;
+    }
   }
   Vaa *= h1r * h1t;
   Vba *= h2r * h1t;

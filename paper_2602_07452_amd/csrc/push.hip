@@ -70,17 +70,73 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
 }
 
 // --------------------------------------------------------------- F(z)
-// F at z, with s, c = sin, cos of z[1]
+// F at z (eqs. p1, p2, O1, O2), with s, c = sin, cos of z[1]; *pw = the
+// power (q/m) E_i dx^i/dt, *e (optional) = alpha Gamma - beta^r u_r.
+// The metric derivatives enter the gravity force only contracted with the
+// momenta, u_l u_m d_k gamma^lm; with P = rho^2, S = P + 2r, xi = S/P and
+// s2 = sin^2 theta that contraction is
+//   -dP_k / P^2 (a^2 s2 u_r^2 + u_th^2 + u_ph^2 / s2 + 2 a u_r u_ph)
+//   + d(s2)_k / P (a^2 u_r^2 - u_ph^2 / s2^2) - d(xi)_k / xi^2 u_r^2,
+// evaluated in that factored form (fewer live values than the twelve
+// derivatives; equal to rounding).
 template <bool GRID>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      const double* z, double s, double c, double* f,
                                      double* pw, double* e = nullptr) {
-  Met m;
-  DMet d;
-  metric_d_sc(A.a, z[0], s, c, m, d);
+  const double a = A.a, a2 = a * a, r = z[0], ur = z[3], ut = z[4], up = z[5];
+  const double s2 = s * s, sc = s * c;
+  const double rho2 = r * r + a2 * c * c, S = rho2 + 2.0 * r;
+  const double irho2 = rcp(rho2), iS = rcp(S), is2 = rcp(s2);
+  const double ixi = rho2 * iS, alpha = fsqrt(ixi), betar = 2.0 * r * iS;
+  const double sg = fabs(s) * fsqrt(rho2 * S);
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
-  if (GRID && qm != 0.0) gather(A.g, A.f, z[0], z[1], rcp(m.sg), D, B);
-  rhs(qm, z, m, d, D, B, f, pw, e);
+  if (GRID && qm != 0.0) gather(A.g, A.f, r, z[1], rcp(sg), D, B);
+  // contravariant momentum gamma^ij u_j and the Lorentz factor
+  const double irp = a * irho2;
+  const double Ur = (a2 * s2 * irho2 + ixi) * ur + irp * up;
+  const double Ut = irho2 * ut;
+  const double Up = irp * ur + irho2 * is2 * up;
+  const double G = fsqrt(1.0 + ur * Ur + ut * Ut + up * Up), iG = rcp(G);
+  const double aiG = alpha * iG;
+  if (e) *e = alpha * G - betar * ur;
+  f[0] = aiG * Ur - betar;
+  f[1] = aiG * Ut;
+  f[2] = aiG * Up;
+  // gravity: -Gamma d_k alpha + u_r d_k beta^r - alpha/(2 Gamma) u u d_k gamma^-1
+  const double i4 = irho2 * irho2, ixi2 = ixi * ixi, ur2 = ur * ur;
+  const double Aq = a2 * s2 * ur2 + ut * ut + up * up * is2 + 2.0 * a * ur * up;
+  const double Bq = irho2 * (a2 * ur2 - up * up * is2 * is2);
+  const double Cq = 0.5 * G * alpha * ixi + ur * ixi2 + 0.5 * aiG * ixi2 * ur2;
+  const double dxr = 2.0 * irho2 * (1.0 - 2.0 * r * r * irho2);  // d_r xi
+  const double dxt = 4.0 * r * a2 * sc * i4;                      // d_theta xi
+  const double gr = dxr * Cq + aiG * r * i4 * Aq;
+  const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
+  if (qm != 0.0) {
+    // Lorentz force: alpha (q/m) [gamma_ij D^j + sqrt(g) eta_ijk U^j B^k / Gamma]
+    const double xi = S * irho2;
+    const double Dl_r = xi * (D[0] - a * s2 * D[2]);
+    const double Dl_t = rho2 * D[1];
+    const double Dl_p = s2 * (-a * xi * D[0] + (rho2 + a2 * xi * s2) * D[2]);
+    const double sgiG = sg * iG;
+    const double cr = Ut * B[2] - Up * B[1];
+    const double ct = Up * B[0] - Ur * B[2];
+    const double cp = Ur * B[1] - Ut * B[0];
+    const double qa = qm * alpha;
+    f[3] = gr + qa * (Dl_r + sgiG * cr);
+    f[4] = gt + qa * (Dl_t + sgiG * ct);
+    f[5] = qa * (Dl_p + sgiG * cp);
+    // E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei)
+    const double sgb = sg * betar;
+    const double Er = alpha * Dl_r;
+    const double Et = alpha * Dl_t - sgb * B[2];
+    const double Ep = alpha * Dl_p + sgb * B[1];
+    *pw = qm * (Er * f[0] + Et * f[1] + Ep * f[2]);
+  } else {
+    f[3] = gr;
+    f[4] = gt;
+    f[5] = 0.0;
+    *pw = 0.0;
+  }
 }
 
 // RK4; *e0 = energy e at z (from the first stage)
