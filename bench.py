@@ -100,12 +100,13 @@ def rplus(a):
 
 WORKLOADS = {
     "c3": dict(
-        desc=("full PIC cycle, plasma-filled Wald magnetosphere: Kerr a=0.99, "
+        desc=("full PIC cycle, plasma-filled Wald magnetosphere: Kerr a=0.99 started "
+              "with the a=0 Wald field (grid E=0, D=-beta x B/alpha), "
               "1024x1024 (r,theta) grid r in [0.9 r+, 20], absorbing layer from 18, "
               "2^24 e+/e- macro-particles uniform in proper volume, Maxwell-Juettner "
               "Theta=0.1, FDTD + gather + Hyb2 push (RK4 -> IMR) + conserving deposit"),
         a=0.99, nr=1024, nth=1024, r_out=20.0, n=1 << 24, mode="evolve",
-        pusher="hyb2", thr=1e-13, theta=0.1, r_abs=18.0),
+        pusher="hyb2", thr=1e-13, theta=0.1, r_abs=18.0, a_field=0.0),
     "c5": dict(
         desc=("full PIC cycle, split-monopole magnetosphere: Kerr a=0.9, 2048x2048 (r,theta) "
               "grid r in [0.9 r+, 100], absorbing layer from 90, 2^27 e+/e- macro-particles "
@@ -158,7 +159,7 @@ def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
     if W.get("fields") == "monopole":
         ctx.set_fields_split_monopole(1.0, 1e3)
     else:
-        ctx.set_fields_wald(1.0)
+        ctx.set_fields_wald(1.0, a_field=W.get("a_field"))
     if evolve:
         # weight: plasma frequency omega_p dt = 0.05 at the mean density
         # (4 pi n q^2/m = omega_p^2, n = N w / V, V ~ proper shell volume)
@@ -208,7 +209,7 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
     if W.get("fields") == "monopole":
         D, B = O.split_monopole_grid(g, 1.0, 1e3)
     else:
-        D, B = O.wald_grid(g, 1.0)
+        D, B = O.wald_grid(g, 1.0, a_field=W.get("a_field"))
     G6 = [g.densitize(c, D[c]) for c in range(3)] + [g.densitize(3 + c, B[c]) for c in range(3)]
     evolve = W["mode"] == "evolve"
     if evolve:

@@ -151,9 +151,15 @@ int grpic_grid_coords(grpic_ctx *ctx, double *rn, double *rh, double *tn,
                       double *th);
 
 /* ---- fields ----------------------------------------------------------- */
-/* Wald vacuum field of strength B0 on every D and B level (App. B.1, with
- * E_i = +d_i A_0 and D_i from eq. Ei); J and rho are cleared.             */
-int grpic_set_fields_wald(grpic_ctx *ctx, double B0);
+/* Wald field of strength B0 on every D and B level (App. B.1, with
+ * E_i = +d_i A_0 and D_i from eq. Ei); J and rho are cleared.  a_field is
+ * the spin in the potential of eq. Amu, 0 <= a_field < 1: a_field = cfg.a
+ * gives the Wald vacuum solution of the spacetime; a_field = 0 gives the
+ * start of Sec. 3.3 (the Schwarzschild Wald field laid on the Kerr
+ * spacetime: grid E_i = 0, D = -beta x B / alpha).  The densitized B is the
+ * curl of that potential, alpha, beta, gamma those of cfg.a.
+ * GRPIC_E_INVALID for a non-finite B0 or a_field out of range.            */
+int grpic_set_fields_wald(grpic_ctx *ctx, double B0, double a_field);
 /* Split monopole (App. B.2): flux function 4 B0 zeta(theta)(1 - cos theta),
  * zeta = (2/pi) atan(zeta0 (theta - pi/2)); D = 0.                        */
 int grpic_set_fields_split_monopole(grpic_ctx *ctx, double B0, double zeta0);

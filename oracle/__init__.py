@@ -127,10 +127,13 @@ def rhs(a, qm, z, D=(0, 0, 0), B=(0, 0, 0)):
     return f
 
 
-def wald_fields(a, B0, r, th):
+def wald_fields(a, B0, r, th, a_field=None):
+    """D^i, B^i of the Wald field; a_field (default a) is the spin of the
+    potential of eq. Amu, a the spacetime's (Sec. 3.3 uses a_field = 0)."""
     D, B = np.zeros(3), np.zeros(3)
-    lib().om_wald_fields(C.c_double(a), C.c_double(B0), C.c_double(r),
-                         C.c_double(th), _p(D), _p(B))
+    af = a if a_field is None else a_field
+    lib().om_wald_fields_spin(C.c_double(a), C.c_double(af), C.c_double(B0),
+                              C.c_double(r), C.c_double(th), _p(D), _p(B))
     return D, B
 
 
@@ -412,10 +415,11 @@ def poynting(grid, D, B):
 
 
 # ------------------------------------------------------------- initial data
-def wald_grid(grid, B0):
+def wald_grid(grid, B0, a_field=None):
     D = [np.zeros(s) for s in _dshapes(grid)]
     B = [np.zeros(s) for s in _bshapes(grid)]
-    lib().om_wald_grid(grid.h, C.c_double(B0), _ptrs(D), _ptrs(B))
+    af = grid.a if a_field is None else a_field
+    lib().om_wald_grid(grid.h, C.c_double(B0), C.c_double(af), _ptrs(D), _ptrs(B))
     return D, B
 
 

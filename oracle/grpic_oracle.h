@@ -52,6 +52,10 @@ void om_rhs(double a, double qm, const double *z, const double *D,
 /* ---- Wald field (Sec. 3.1.3, App. B.1) --------------------------------- */
 void om_wald_fields(double a, double B0, double r, double th, double *D,
                     double *B);
+/* the potential of eq. Amu taken with spin af in the spacetime of spin a
+ * (af = 0: the Schwarzschild-Wald start of Sec. 3.3, E_i = 0)             */
+void om_wald_fields_spin(double a, double af, double B0, double r, double th,
+                         double *D, double *B);
 /* A[4] = A_0 (form used for the conserved energy), A_r, A_theta, A_phi     */
 void om_wald_potential(double a, double B0, double r, double th, double *A);
 
@@ -183,7 +187,7 @@ void om_poynting(const om_grid *g, const double *const *D,
                  const double *const *B, double *out);
 
 /* ---- initial data (App. B, Sec. 3.3) -------------------------------------*/
-void om_wald_grid(const om_grid *g, double B0, double *const *D,
+void om_wald_grid(const om_grid *g, double B0, double af, double *const *D,
                   double *const *B);
 void om_split_monopole_grid(const om_grid *g, double B0, double zeta0,
                             double *const *D, double *const *B);

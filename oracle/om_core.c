@@ -142,21 +142,29 @@ static double om_power(double a, double qm, const double *z, const double *D,
  * (so E_theta carries a single factor a), D_i from eq. Ei, D^j = gamma^ij
  * D_i.  A_0 in the form used for the conserved energy (Sec. 3.1.3), A_phi
  * with the factor B0, A_r from eq. Amu.
+ *
+ * The potential of eq. Amu may be taken with a spin af of its own while the
+ * spacetime has spin a (Sec. 3.3 starts a Kerr hole with the af = 0 field):
+ * the curl eta^ijk d_j A_k and E_i = d_i A_0 are those of the af solution,
+ * and sqrt(gamma), alpha, beta, gamma^ij those of the spacetime.  af = a is
+ * the Wald vacuum solution itself; af = 0 has A_0 = 0, so E_i = 0 and
+ * D = -beta x B / alpha.
  * ------------------------------------------------------------------------ */
-void om_wald_fields(double a, double B0, double r, double th, double *D,
-                    double *B) {
+void om_wald_fields_spin(double a, double af, double B0, double r, double th,
+                         double *D, double *B) {
   double m[13];
   om_metric(a, r, th, m);
   double s = sin(th), c = cos(th);
-  double rho2 = m[12], rho4 = rho2 * rho2, sg = m[10];
-  double a2 = a * a, r2 = r * r;
+  double a2 = af * af, r2 = r * r;
+  double rho2 = r2 + a2 * c * c, rho4 = rho2 * rho2, sg = m[10];
+  /* eta^ijk d_j A_k of the af potential, divided by the spacetime's sqrt(g) */
   B[0] = B0 / sg * (r2 + a2 - 2.0 * r + 2.0 * r * (r2 * r2 - a2 * a2) / rho4) *
          s * c;
   B[1] = -B0 / sg * (r + a2 * (1.0 + c * c) * (2.0 * r2 - rho2) / rho4) * s *
          s;
-  B[2] = -B0 / sg * (2.0 * a * r * (a2 - r2) / rho4 - a) * s * c;
-  double Er = B0 * a * (1.0 + c * c) * (a2 * c * c - r2) / rho4;
-  double Et = B0 * a * 2.0 * r * (a2 - r2) / rho4 * s * c;
+  B[2] = -B0 / sg * (2.0 * af * r * (a2 - r2) / rho4 - af) * s * c;
+  double Er = B0 * af * (1.0 + c * c) * (a2 * c * c - r2) / rho4;
+  double Et = B0 * af * 2.0 * r * (a2 - r2) / rho4 * s * c;
   double Ep = 0.0;
   double alpha = m[0], betar = m[1];
   double Dr_l = Er / alpha;
@@ -165,6 +173,11 @@ void om_wald_fields(double a, double B0, double r, double th, double *D,
   D[0] = m[6] * Dr_l + m[9] * Dp_l;
   D[1] = m[7] * Dt_l;
   D[2] = m[9] * Dr_l + m[8] * Dp_l;
+}
+
+void om_wald_fields(double a, double B0, double r, double th, double *D,
+                    double *B) {
+  om_wald_fields_spin(a, a, B0, r, th, D, B);
 }
 
 void om_wald_potential(double a, double B0, double r, double th, double *A) {

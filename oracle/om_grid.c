@@ -783,7 +783,7 @@ void om_poynting(const om_grid *g, const double *const *D,
  * the cell edge so that the discrete div B vanishes; B^theta = B^phi = 0,
  * and D = -beta x B / alpha = 0 for a radial B.
  * ------------------------------------------------------------------------ */
-void om_wald_grid(const om_grid *g, double B0, double *const *D,
+void om_wald_grid(const om_grid *g, double B0, double af, double *const *D,
                   double *const *B) {
   for (int c = 0; c < 6; ++c) {
     int nR, nT;
@@ -792,7 +792,8 @@ void om_wald_grid(const om_grid *g, double B0, double *const *D,
     for (int j = 0; j < nT; ++j)
       for (int i = 0; i < nR; ++i) {
         double d[3], b[3];
-        om_wald_fields(g->a, B0, comp_r(g, c, i), comp_t(g, c, j), d, b);
+        om_wald_fields_spin(g->a, af, B0, comp_r(g, c, i), comp_t(g, c, j), d,
+                            b);
         A[IDX(nR, i, j)] = c < 3 ? d[c] : b[c - 3];
       }
   }

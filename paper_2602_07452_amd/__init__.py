@@ -167,8 +167,11 @@ class Context:
             rh, thh = comp == 0, comp == 1
         return (nth if thh else nth + 1, nr if rh else nr + 1)
 
-    def set_fields_wald(self, B0):
-        self._c("grpic_set_fields_wald", C.c_double(B0))
+    def set_fields_wald(self, B0, a_field=None):
+        """Wald field; a_field (default: the spacetime spin) is the spin in
+        the potential, 0 for the Schwarzschild-Wald start."""
+        af = self.cfg.a if a_field is None else a_field
+        self._c("grpic_set_fields_wald", C.c_double(B0), C.c_double(af))
 
     def set_fields_split_monopole(self, B0, zeta0):
         self._c("grpic_set_fields_split_monopole", C.c_double(B0), C.c_double(zeta0))

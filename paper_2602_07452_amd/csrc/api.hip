@@ -637,12 +637,15 @@ int grpic_grid_coords(grpic_ctx* c, double* rn, double* rh, double* tn,
   });
 }
 
-int grpic_set_fields_wald(grpic_ctx* c, double B0) {
+int grpic_set_fields_wald(grpic_ctx* c, double B0, double a_field) {
   return guarded(c, [&] {
     check_ctx(c);
     if (c->nr == 0) throw Error(GRPIC_E_STATE, "context has no grid");
+    if (!std::isfinite(B0)) throw Error(GRPIC_E_INVALID, "B0 must be finite");
+    if (!(a_field >= 0.0 && a_field < 1.0))
+      throw Error(GRPIC_E_INVALID, "a_field must lie in [0, 1)");
     drop_graphs(c);
-    launch_wald(c, B0);
+    launch_wald(c, B0, a_field);
     GRPIC_HIP(hipStreamSynchronize(c->stream));
   });
 }

@@ -164,7 +164,7 @@ struct Error {
 
 // launchers (defined in the .hip translation units)
 void launch_metric_tables(grpic_ctx* c);
-void launch_wald(grpic_ctx* c, double B0);
+void launch_wald(grpic_ctx* c, double B0, double a_field);
 void launch_split_monopole(grpic_ctx* c, double B0, double zeta0);
 void launch_fields_step_pre(grpic_ctx* c);   // sub-steps 1-4
 void launch_fields_step_post(grpic_ctx* c);  // sub-steps 7-10

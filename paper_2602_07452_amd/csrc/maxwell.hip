@@ -92,19 +92,23 @@ void launch_metric_tables(grpic_ctx* c) {
 // App. B.1: B^i from the closed forms, E_r = d_r A_0, E_theta = d_theta A_0
 // (one factor of a), E_phi = 0, A_0 = B0 a r (1 + cos^2) / rho^2;
 // D_i = (E_i - sqrt(g) eta_ijk beta^j B^k) / alpha, D^i = gamma^ij D_j.
-__device__ void wald_point(double a, double B0, double r, double th,
+// The potential of eq. Amu carries its own spin af: the curl (sqrt(g) B^i,
+// the stored densitized value) and E_i come from the af solution, alpha,
+// beta, gamma from the spacetime.  af = 0 is the start of Sec. 3.3: E_i = 0,
+// D = -beta x B / alpha.
+__device__ void wald_point(double a, double af, double B0, double r, double th,
                            double* D, double* B, double& sg) {
   Met m;
   metric(a, r, th, m);
   double s = m.s, c = m.c;
-  double a2 = a * a, r2 = r * r;
+  double a2 = af * af, r2 = r * r;
   double rho2 = r2 + a2 * c * c, irho4 = 1.0 / (rho2 * rho2);
   double isg = 1.0 / m.sg;
   B[0] = B0 * isg * (r2 + a2 - 2.0 * r + 2.0 * r * (r2 * r2 - a2 * a2) * irho4) * s * c;
   B[1] = -B0 * isg * (r + a2 * (1.0 + c * c) * (2.0 * r2 - rho2) * irho4) * s * s;
-  B[2] = -B0 * isg * (2.0 * a * r * (a2 - r2) * irho4 - a) * s * c;
-  double Er = B0 * a * (1.0 + c * c) * (a2 * c * c - r2) * irho4;
-  double Et = B0 * a * 2.0 * r * (a2 - r2) * irho4 * s * c;
+  B[2] = -B0 * isg * (2.0 * af * r * (a2 - r2) * irho4 - af) * s * c;
+  double Er = B0 * af * (1.0 + c * c) * (a2 * c * c - r2) * irho4;
+  double Et = B0 * af * 2.0 * r * (a2 - r2) * irho4 * s * c;
   double ia = 1.0 / m.alpha;
   double Dr = Er * ia;
   double Dt = (Et + m.sg * m.betar * B[2]) * ia;
@@ -116,7 +120,7 @@ __device__ void wald_point(double a, double B0, double r, double th,
 }
 
 struct IcArgs {
-  double a, B0, zeta0;
+  double a, a_field, B0, zeta0;
   int nr, nth;
   const double *rn, *rh, *tn, *th;
   float* D[3][3];  // [level][comp]
@@ -136,7 +140,7 @@ __global__ void k_wald(IcArgs A, int comp) {
   double r = rhalf ? A.rh[i] : A.rn[i];
   double th = thalf ? A.th[j] : A.tn[j];
   double D[3], B[3], sg;
-  wald_point(A.a, A.B0, r, th, D, B, sg);
+  wald_point(A.a, A.a_field, A.B0, r, th, D, B, sg);
   float v = (float)(sg * (comp < 3 ? D[comp] : B[comp - 3]));
   for (int l = 0; l < 3; ++l) {
     if (comp < 3)
@@ -179,9 +183,10 @@ static IcArgs ic_args(grpic_ctx* c) {
   return A;
 }
 
-void launch_wald(grpic_ctx* c, double B0) {
+void launch_wald(grpic_ctx* c, double B0, double a_field) {
   IcArgs A = ic_args(c);
   A.B0 = B0;
+  A.a_field = a_field;
   long n = (long)(c->nr + 1) * (c->nth + 1);
   for (int comp = 0; comp < 6; ++comp) {
     hipLaunchKernelGGL(k_wald, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,

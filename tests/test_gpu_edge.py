@@ -181,3 +181,35 @@ def test_schwarzschild_full_step():
          [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
     err, _ = compare_push(cfg, P0, P1, push_params_from(cfg, O.FIELDS_GRID), grid=g, G6=G6)
     assert err <= TOL_STATE
+
+
+def test_schwarzschild_wald_start_full_steps():
+    """Sec. 3.3: a = 0.999 spacetime started with the a = 0 Wald field (grid
+    E_i = 0, D = -beta x B / alpha) and a pair plasma; the initial fields
+    match the oracle's, then one full cycle after two steps matches too."""
+    cfg = _pic_cfg(a=0.999, n=3000)
+    g = oracle_grid(cfg)
+    D, B = O.wald_grid(g, 1.0, a_field=0.0)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0, a_field=0.0)
+        for lev in (G.LEVEL_DN, G.LEVEL_BN):
+            arrs, off = (D, 0) if lev == G.LEVEL_DN else (B, 3)
+            for c in range(3):
+                assert norm_err(ctx.get_field(lev, c), g.densitize(off + c, arrs[c])) < 1e-6
+        assert np.abs(ctx.get_field(G.LEVEL_BN, 2)).max() == 0.0  # B^phi = 0
+        ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 33, rplus(cfg.a), 18.0,
+                           cfg.theta0, np.pi - cfg.theta0, 0.1, w=2e-3)
+        ctx.step(2)
+        S0 = _levels(ctx)
+        P0 = ctx.get_particles()
+        ctx.step(1)
+        S1 = _levels(ctx)
+        P1 = ctx.get_particles()
+    F = _oracle_fields(g, S0)
+    O.pic_step(push_params_from(cfg, O.FIELDS_GRID), g, F, oracle_particles(P0),
+               absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
+    assert not _field_errors(g, F, S1)
+    G6 = [S0[G.LEVEL_DH1][c].astype(np.float64) for c in range(3)] + \
+         [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
+    err, _ = compare_push(cfg, P0, P1, push_params_from(cfg, O.FIELDS_GRID), grid=g, G6=G6)
+    assert err <= TOL_STATE

@@ -88,12 +88,15 @@ def _wald_cfg(pusher, thr=0.0, n=3000, nr=64, nth=48, dt=0.02, guess=G.GUESS_PLA
                             r_remove_out=50.0, reflect=1, guess=guess)
 
 
-def test_wald_grid_fields_match_oracle():
+@pytest.mark.parametrize("a_field", [None, 0.0, 0.5])
+def test_wald_grid_fields_match_oracle(a_field):
+    """Wald field of the spacetime's spin (default), the Schwarzschild-Wald
+    start (a_field = 0, Sec. 3.3) and a third spin, on every Yee subgrid."""
     cfg = _wald_cfg(G.PUSH_RK4)
     g = oracle_grid(cfg)
-    D, B = O.wald_grid(g, 1.0)
+    D, B = O.wald_grid(g, 1.0, a_field=a_field)
     with G.Context(cfg) as ctx:
-        ctx.set_fields_wald(1.0)
+        ctx.set_fields_wald(1.0, a_field=a_field)
         for lev, arrs, off in ((G.LEVEL_DH1, D, 0), (G.LEVEL_BH, B, 3), (G.LEVEL_DN, D, 0),
                                (G.LEVEL_BM, B, 3)):
             for c in range(3):

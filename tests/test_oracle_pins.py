@@ -129,14 +129,17 @@ def test_charged_wald_conserves_H_and_L(a, qm):
         assert abs(gL @ f) < 1e-8 * max(np.abs(f).max() * np.abs(gL).max(), 1)
 
 
-@pytest.mark.parametrize("a", [0.0, 0.9, 0.99])
-def test_wald_field_is_curl_of_potential(a):
+@pytest.mark.parametrize("a,af", [(0.0, 0.0), (0.9, 0.9), (0.99, 0.99), (0.999, 0.0),
+                                  (0.9, 0.5)])
+def test_wald_field_is_curl_of_potential(a, af):
     """App. B.1: B^i = eta^ijk d_j A_k / sqrt(g); E_i = d_i A_0; E_phi = 0,
-    with E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei)."""
+    with E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k (eq. Ei).  The
+    potential may carry its own spin af (Sec. 3.3): curl and A_0 from the af
+    potential, sqrt(g), alpha, beta, gamma from the spacetime's a."""
     B0, h = 1.3, 1e-6
     for r, th in zip(*_rand_points(10, a, 1.6, 15)):
-        D, B = O.wald_fields(a, B0, r, th)
-        A = lambda rr, tt: O.wald_potential(a, B0, rr, tt)
+        D, B = O.wald_fields(a, B0, r, th, a_field=af)
+        A = lambda rr, tt: O.wald_potential(af, B0, rr, tt)
         dA_r = (A(r + h, th) - A(r - h, th)) / (2 * h)
         dA_t = (A(r, th + h) - A(r, th - h)) / (2 * h)
         m = O.metric(a, r, th)
@@ -147,6 +150,34 @@ def test_wald_field_is_curl_of_potential(a):
         Dl = np.array([[m[2], 0, m[5]], [0, m[3], 0], [m[5], 0, m[4]]]) @ D
         E = m[0] * Dl + sg * m[1] * np.array([0.0, -B[2], B[1]])
         assert np.allclose(E, [dA_r[0], dA_t[0], 0.0], rtol=1e-7, atol=1e-9)
+    # the spin-a default is the af = a field
+    assert np.array_equal(np.r_[O.wald_fields(a, B0, 3.0, 1.0)],
+                          np.r_[O.wald_fields(a, B0, 3.0, 1.0, a_field=a)])
+
+
+@pytest.mark.parametrize("a", [0.7, 0.999])
+def test_schwarzschild_wald_start_in_kerr(a):
+    """Sec. 3.3: a Kerr hole started with the a = 0 Wald field.  A_phi is
+    B0 r^2 sin^2(theta) / 2 and A_0 = A_r = 0, so sqrt(g) B^r =
+    B0 r^2 sin cos, sqrt(g) B^theta = -B0 r sin^2, B^phi = 0; the grid field
+    E_i vanishes, D = -beta x B / alpha, and D_i B^i = 0 everywhere."""
+    B0 = 1e3
+    for r, th in zip(*_rand_points(12, a, 1.02 * _rplus(a), 20)):
+        D, B = O.wald_fields(a, B0, r, th, a_field=0.0)
+        m = O.metric(a, r, th)
+        sg, s, c = m[10], np.sin(th), np.cos(th)
+        assert np.isclose(B[0] * sg, B0 * r * r * s * c, rtol=1e-13, atol=1e-13 * B0)
+        assert np.isclose(B[1] * sg, -B0 * r * s * s, rtol=1e-13)
+        assert B[2] == 0.0
+        Dl = np.array([[m[2], 0, m[5]], [0, m[3], 0], [m[5], 0, m[4]]]) @ D
+        # (beta x B)_i = sqrt(g) eta_ijk beta^j B^k with beta = (beta^r, 0, 0)
+        bxB = sg * m[1] * np.array([0.0, -B[2], B[1]])
+        assert np.allclose(Dl, -bxB / m[0], rtol=1e-12, atol=1e-12 * B0)
+        assert abs(Dl @ B) <= 1e-12 * np.linalg.norm(Dl) * np.linalg.norm(B) + 1e-300
+    # and it differs from the Kerr Wald field of the same spacetime
+    Dk, Bk = O.wald_fields(a, B0, 3.0, 1.0)
+    D0, B0f = O.wald_fields(a, B0, 3.0, 1.0, a_field=0.0)
+    assert not np.allclose(Bk, B0f, rtol=1e-3)
 
 
 @pytest.mark.parametrize("a", [0.0, 0.9, 0.99])
