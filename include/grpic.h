@@ -216,6 +216,43 @@ int grpic_num_particles(grpic_ctx *ctx, long *n);
 int grpic_sample_particles(grpic_ctx *ctx, long m, const long *ids,
                            double *rec, int32_t *flags, int32_t *iters);
 
+/* ---- state snapshot (checkpoint / resume) ------------------------------ */
+/* A snapshot is one host byte block: a grpic_state_header, then every
+ * field level (D^{n+1}, D^{n+1/2}, D^{n+3/2}, B^n, B^{n+1}, B^{n+3/2}: 3
+ * FP32 components each; J, J_prev: 4 each; in level and component order,
+ * each of its own shape) when the context has a grid, then the particles in
+ * storage order (r, theta, phi, u_r, u_theta, u_phi, H0, herr, w as FP64;
+ * q/m as int8; flags, iters as uint8; id as uint32; with a grid the
+ * deposit weights W1..W3 of the current position as FP64 and the cell
+ * index as int32), then the diagnostic counters.  Restoring it into a
+ * context of the same grid, field mode and dt continues the run exactly as
+ * the uninterrupted one (the deposit sums are order-independent).  The
+ * learned-guess network is not part of it (grpic_mlp_get / grpic_mlp_set). */
+typedef struct grpic_state_header {
+  char magic[8];          /* "GRPICST" and a zero byte                      */
+  int32_t version;        /* 1                                              */
+  int32_t field_mode;     /* enum grpic_field_mode                          */
+  int32_t nr, nth;        /* grid cells                                     */
+  double a, r_in, r_out, theta0, dt;
+  int64_t n;              /* particles                                      */
+  int64_t steps;          /* steps taken since the particles were loaded    */
+  double qw_max;          /* largest |q w| (the deposit's fixed-point unit) */
+  int32_t has_neutral;    /* some particle has q/m = 0                      */
+  int32_t reserved;
+  uint64_t bytes;         /* size of the whole snapshot, header included    */
+} grpic_state_header;
+/* Size in bytes of a snapshot of the context as it is now.               */
+int grpic_state_size(grpic_ctx *ctx, size_t *bytes);
+/* Write the snapshot into host[0..bytes); GRPIC_E_INVALID if bytes is
+ * smaller than grpic_state_size.  Synchronizes the context's stream.      */
+int grpic_get_state(grpic_ctx *ctx, void *host, size_t bytes);
+/* Replace the context's fields, particles, step count and counters by a
+ * snapshot.  GRPIC_E_INVALID if the block is short, not a snapshot, or
+ * taken on another grid (nr, nth, a, r_in, r_out, theta0), field mode or
+ * dt, or holds more particles than max_particles.  Cached step graphs are
+ * dropped.                                                                */
+int grpic_set_state(grpic_ctx *ctx, const void *host, size_t bytes);
+
 /* ---- stepping ---------------------------------------------------------- */
 /* Advance nsteps steps, asynchronously on the context's stream.           */
 int grpic_step(grpic_ctx *ctx, int nsteps);

@@ -241,6 +241,21 @@ class Context:
         out["z"] = rec[:, :6].copy()
         return out
 
+    # -- snapshots
+    def get_state(self):
+        """The context's snapshot (header, fields, particles, counters) as a
+        uint8 array."""
+        nb = C.c_size_t()
+        self._c("grpic_state_size", C.byref(nb))
+        buf = np.zeros(nb.value, np.uint8)
+        self._c("grpic_get_state", buf.ctypes.data_as(C.c_void_p), C.c_size_t(nb.value))
+        return buf
+
+    def set_state(self, buf):
+        """Restore a snapshot taken by get_state() (same grid, mode, dt)."""
+        buf = np.ascontiguousarray(np.frombuffer(buf, np.uint8))
+        self._c("grpic_set_state", buf.ctypes.data_as(C.c_void_p), C.c_size_t(buf.size))
+
     # -- stepping
     def step(self, nsteps=1):
         self._c("grpic_step", C.c_int(nsteps))
@@ -341,6 +356,19 @@ class Context:
         self._c("grpic_mlp_loss_grad", C.c_long(X.shape[0]), X.ctypes.data_as(fp),
                 T.ctypes.data_as(fp), g.ctypes.data_as(fp), C.byref(loss))
         return loss.value, g
+
+
+class StateHeader(C.Structure):
+    _fields_ = [("magic", C.c_char * 8), ("version", C.c_int32), ("field_mode", C.c_int32),
+                ("nr", C.c_int32), ("nth", C.c_int32), ("a", C.c_double), ("r_in", C.c_double),
+                ("r_out", C.c_double), ("theta0", C.c_double), ("dt", C.c_double),
+                ("n", C.c_int64), ("steps", C.c_int64), ("qw_max", C.c_double),
+                ("has_neutral", C.c_int32), ("reserved", C.c_int32), ("bytes", C.c_uint64)]
+
+
+def state_header(buf):
+    """The header of a snapshot block."""
+    return StateHeader.from_buffer_copy(bytes(np.asarray(buf, np.uint8)[:C.sizeof(StateHeader)]))
 
 
 class TuneResult(C.Structure):

@@ -1149,3 +1149,129 @@ int grpic_autotune(grpic_ctx* c, int trial_steps, grpic_tune_result* out) {
     c->cfg.sort_every = sort_every;
   });
 }
+
+// ------------------------------------------------------ state snapshots
+namespace {
+
+struct StateItem {
+  void* d;
+  size_t bytes;
+};
+
+// the device arrays of a snapshot, in snapshot order, for n particles
+std::vector<StateItem> state_items(grpic_ctx* c, long n) {
+  std::vector<StateItem> v;
+  if (c->nr > 0) {
+    for (int lev = GRPIC_LEVEL_DN; lev <= GRPIC_LEVEL_JPREV; ++lev) {
+      int nc = lev >= GRPIC_LEVEL_J ? 4 : 3;
+      for (int q = 0; q < nc; ++q)
+        v.push_back({level_ptr(c, lev, q), sizeof(float) * comp_size(c, lev, q)});
+    }
+  }
+  const ParticleView& P = c->pv;
+  size_t d = sizeof(double) * (size_t)n;
+  for (double* a : {P.r, P.th, P.ph, P.ur, P.uth, P.uph, P.H0, P.herr, P.w})
+    v.push_back({a, d});
+  v.push_back({P.qm, (size_t)n});
+  v.push_back({P.flags, (size_t)n});
+  v.push_back({P.iters, (size_t)n});
+  v.push_back({P.id, sizeof(uint32_t) * (size_t)n});
+  if (P.cell) {
+    for (int q = 1; q < 4; ++q) v.push_back({P.W[q], d});
+    v.push_back({P.cell, sizeof(int) * (size_t)n});
+  }
+  v.push_back({c->stats, sizeof(Stats)});
+  return v;
+}
+
+size_t state_bytes(const std::vector<StateItem>& v) {
+  size_t b = sizeof(grpic_state_header);
+  for (const StateItem& s : v) b += s.bytes;
+  return b;
+}
+
+const char kStateMagic[8] = {'G', 'R', 'P', 'I', 'C', 'S', 'T', 0};
+
+}  // namespace
+
+extern "C" {
+
+int grpic_state_size(grpic_ctx* c, size_t* bytes) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!bytes) throw Error(GRPIC_E_INVALID, "null pointer");
+    *bytes = state_bytes(state_items(c, c->n));
+  });
+}
+
+int grpic_get_state(grpic_ctx* c, void* host, size_t bytes) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!host) throw Error(GRPIC_E_INVALID, "null host buffer");
+    std::vector<StateItem> items = state_items(c, c->n);
+    size_t need = state_bytes(items);
+    if (bytes < need) throw Error(GRPIC_E_INVALID, "buffer smaller than the snapshot");
+    grpic_state_header h{};
+    std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
+    h.version = 1;
+    h.field_mode = c->cfg.field_mode;
+    h.nr = c->nr;
+    h.nth = c->nth;
+    h.a = c->cfg.a;
+    h.r_in = c->cfg.r_in;
+    h.r_out = c->cfg.r_out;
+    h.theta0 = c->cfg.theta0;
+    h.dt = c->cfg.dt;
+    h.n = c->n;
+    h.steps = c->steps;
+    h.qw_max = c->qw_max;
+    h.has_neutral = c->has_neutral ? 1 : 0;
+    h.bytes = need;
+    GRPIC_HIP(hipStreamSynchronize(c->stream));
+    char* out = static_cast<char*>(host);
+    std::memcpy(out, &h, sizeof(h));
+    size_t off = sizeof(h);
+    for (const StateItem& s : items) {
+      if (s.bytes) GRPIC_HIP(hipMemcpy(out + off, s.d, s.bytes, hipMemcpyDeviceToHost));
+      off += s.bytes;
+    }
+  });
+}
+
+int grpic_set_state(grpic_ctx* c, const void* host, size_t bytes) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!host) throw Error(GRPIC_E_INVALID, "null host buffer");
+    grpic_state_header h;
+    if (bytes < sizeof(h)) throw Error(GRPIC_E_INVALID, "block shorter than a snapshot header");
+    std::memcpy(&h, host, sizeof(h));
+    if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0 || h.version != 1)
+      throw Error(GRPIC_E_INVALID, "not a snapshot of this library");
+    if (h.field_mode != c->cfg.field_mode || h.nr != c->nr || h.nth != c->nth ||
+        h.a != c->cfg.a || h.dt != c->cfg.dt ||
+        (c->nr > 0 && (h.r_in != c->cfg.r_in || h.r_out != c->cfg.r_out ||
+                       h.theta0 != c->cfg.theta0)))
+      throw Error(GRPIC_E_INVALID, "snapshot taken on another grid, field mode or dt");
+    if (h.n < 0 || h.n > c->cap) throw Error(GRPIC_E_INVALID, "snapshot exceeds max_particles");
+    std::vector<StateItem> items = state_items(c, (long)h.n);
+    size_t need = state_bytes(items);
+    if (h.bytes != need || bytes < need)
+      throw Error(GRPIC_E_INVALID, "snapshot size does not match its header");
+    drop_graphs(c);
+    GRPIC_HIP(hipStreamSynchronize(c->stream));
+    const char* in = static_cast<const char*>(host);
+    size_t off = sizeof(h);
+    for (const StateItem& s : items) {
+      if (s.bytes) GRPIC_HIP(hipMemcpy(s.d, in + off, s.bytes, hipMemcpyHostToDevice));
+      off += s.bytes;
+    }
+    c->n = (long)h.n;
+    c->steps = (long)h.steps;
+    c->qw_max = h.qw_max;
+    c->has_neutral = h.has_neutral != 0;
+    if (c->cfg.field_mode == GRPIC_FIELDS_EVOLVE)
+      c->acc.scale = c->qw_max > 0.0 ? ldexp(1.0, 40) / c->qw_max : 1.0;
+  });
+}
+
+}  // extern "C"

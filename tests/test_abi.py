@@ -26,7 +26,8 @@ def test_config_default():
                                        (G.InitSpec, "grpic_init_spec"),
                                        (G.Diag, "grpic_diag"),
                                        (G.MlpTrainConfig, "grpic_mlp_train_config"),
-                                       (G.TuneResult, "grpic_tune_result")])
+                                       (G.TuneResult, "grpic_tune_result"),
+                                       (G.StateHeader, "grpic_state_header")])
 def test_struct_layout_matches_header(cls, cname, tmp_path):
     """The ctypes mirrors have the C structs' size and field offsets."""
     fields = [f[0] for f in cls._fields_]
