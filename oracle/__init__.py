@@ -36,21 +36,22 @@ class PushParams(C.Structure):
                 ("kmax", C.c_int), ("field_kind", C.c_int), ("B0", C.c_double),
                 ("r_min", C.c_double), ("r_max", C.c_double),
                 ("th_lo", C.c_double), ("th_hi", C.c_double),
-                ("ham_eps", C.c_double)]
+                ("ham_eps", C.c_double), ("dt_impl", C.c_double), ("t_end", C.c_double)]
 
 
 def push_params(a, dt, pusher=RK4, guess=GUESS_PLAIN, thr=0.0, tol=1e-13,
                 kmax=50, field_kind=FIELDS_NONE, B0=0.0, r_min=0.0,
-                r_max=1e300, th_lo=-1.0, th_hi=10.0, ham_eps=1e-10):
+                r_max=1e300, th_lo=-1.0, th_hi=10.0, ham_eps=1e-10, dt_impl=0.0,
+                t_end=0.0):
     return PushParams(a, dt, pusher, guess, thr, tol, kmax, field_kind, B0,
-                      r_min, r_max, th_lo, th_hi, ham_eps)
+                      r_min, r_max, th_lo, th_hi, ham_eps, dt_impl, t_end)
 
 
 class _OmParticles(C.Structure):
     _fields_ = [("n", C.c_long)] + [(k, D_P) for k in
                                     ("r", "th", "ph", "ur", "uth", "uph", "qm",
                                      "w", "H0", "herr")] + \
-               [("flags", I_P), ("iters", I_P), ("crit", D_P)]
+               [("flags", I_P), ("iters", I_P), ("crit", D_P), ("t", D_P)]
 
 
 class _OmFields(C.Structure):
@@ -206,6 +207,7 @@ class Particles:
         self.crit[:] = np.nan
         self.flags = np.full(self.n, ALIVE, dtype=np.int32)
         self.iters = np.zeros(self.n, dtype=np.int32)
+        self.t = None  # own clocks (an array) or none
 
     @classmethod
     def from_state(cls, z, qm, w=None, H0=None):
@@ -227,13 +229,17 @@ class Particles:
             getattr(q, k)[:] = getattr(self, k)
         q.flags[:] = self.flags
         q.iters[:] = self.iters
+        q.t = None if self.t is None else self.t.copy()
         return q
 
     def _struct(self):
         for k in self.KEYS:
             assert getattr(self, k).dtype == np.float64 and getattr(self, k).flags.c_contiguous
+        if self.t is not None:
+            assert self.t.dtype == np.float64 and self.t.flags.c_contiguous
         s = _OmParticles(self.n, *[_p(getattr(self, k)) for k in self.KEYS[:10]],
-                         _ip(self.flags), _ip(self.iters), _p(self.crit))
+                         _ip(self.flags), _ip(self.iters), _p(self.crit),
+                         _p(self.t) if self.t is not None else None)
         return s
 
 

@@ -101,6 +101,10 @@ typedef struct {
   double r_min, r_max; /* particles outside are removed                   */
   double th_lo, th_hi; /* reflecting edges; th_lo < 0 disables            */
   double ham_eps;   /* |dx| below which Ham-DG uses analytic derivatives   */
+  double dt_impl;   /* step of the implicit scheme (0: dt); Table 2 pairs a
+                       Delta t_RK4 with a larger Delta t_Ham               */
+  double t_end;     /* with particle clocks: steps are clipped to end at
+                       t_end and particles that reached it stay (0: none) */
 } om_push_params;
 
 typedef struct {
@@ -113,6 +117,8 @@ typedef struct {
   int *flags;   /* OM_ALIVE | ...                                          */
   int *iters;   /* implicit iterations of the last step (0 = explicit)     */
   double *crit; /* RK4 trial criterion of the last step (NaN if none)      */
+  double *t;    /* each particle's own time, advanced by the step it took
+                   (NULL: no clocks, every step is dt)                     */
 } om_particles;
 
 /* one step of every alive particle.  G: 6 densitized field arrays (only for

@@ -451,17 +451,36 @@ static double crit_value(const om_push_params *P, double qm, double H0,
   return fabs(om_energy(P->a, zn) - e0 - Wq) / fabs(e0);
 }
 
-static void push_one(const om_push_params *P, const om_grid *g,
+/* Steps of their own length (Sec. 3.1.2 with Table 2): the explicit trial
+ * advances by dt, the implicit scheme by dt_impl; with particle clocks each
+ * particle's time grows by the step it took, and with t_end both lengths
+ * are clipped to the time left, so every particle ends exactly at t_end and
+ * then stays (flags ALIVE, no iterations, state and criterion unchanged). */
+static void push_one(const om_push_params *P0, const om_grid *g,
                      const double *const *G, om_particles *p, long k,
                      const double *guess, int force) {
   int fl = p->flags[k];
   if (!(fl & OM_ALIVE)) return;
   fl &= OM_ALIVE;
+  p->crit[k] = NAN;
+  om_push_params Pe = *P0, Pi = *P0; /* explicit, implicit step lengths */
+  Pi.dt = P0->dt_impl > 0.0 ? P0->dt_impl : P0->dt;
+  int end_e = 0, end_i = 0; /* the step reaches t_end                      */
+  if (p->t && P0->t_end > 0.0) {
+    double left = P0->t_end - p->t[k];
+    if (!(left > 0.0)) {
+      p->flags[k] = OM_ALIVE;
+      p->iters[k] = 0;
+      return;
+    }
+    if (left <= Pe.dt) Pe.dt = left, end_e = 1;
+    if (left <= Pi.dt) Pi.dt = left, end_i = 1;
+  }
+  const om_push_params *P = &Pe;
   double z[6] = {p->r[k], p->th[k], p->ph[k], p->ur[k], p->uth[k], p->uph[k]};
   double qm = p->qm[k], out[6], trial[6], Wq = 0.0;
   int it = 0;
   double herr_new;
-  p->crit[k] = NAN;
   int implicit = 0;
   if (P->pusher == OM_RK4) {
     om_step_rk4(P, g, G, qm, z, out, &Wq);
@@ -489,9 +508,9 @@ static void push_one(const om_push_params *P, const om_grid *g,
     if (P->guess == OM_GUESS_RK4 && P->pusher >= OM_HYB1) gs = trial;
     if (P->guess == OM_GUESS_EXTERNAL && guess) gs = guess + 6 * k;
     if (qm == 0.0 && P->pusher != OM_IMR)
-      it = om_step_ham(P, z, gs, out), Wq = 0.0;
+      it = om_step_ham(&Pi, z, gs, out), Wq = 0.0;
     else
-      it = om_step_imr(P, g, G, qm, z, gs, out, &Wq);
+      it = om_step_imr(&Pi, g, G, qm, z, gs, out, &Wq);
     fl |= OM_IMPLICIT;
     if (it < 0) fl |= OM_NOCONV, it = -it;
   }
@@ -519,6 +538,13 @@ static void push_one(const om_push_params *P, const om_grid *g,
   p->herr[k] = herr_new;
   p->flags[k] = fl;
   p->iters[k] = it;
+  if (p->t) {
+    /* a step clipped to the time left lands on t_end exactly */
+    if (implicit ? end_i : end_e)
+      p->t[k] = P0->t_end;
+    else
+      p->t[k] += implicit ? Pi.dt : Pe.dt;
+  }
 }
 
 void om_push(const om_push_params *P, const om_grid *g,

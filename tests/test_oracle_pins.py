@@ -419,6 +419,104 @@ def test_charged_energy_budget_residual_is_rk4_local_error():
     assert 20 < vals[0] / vals[1] < 45
 
 
+# --------------------------------------- own step lengths (Sec. 3.1.2, Table 2)
+def _clocked(p):
+    p = p.copy()
+    p.t = np.zeros(p.n)
+    return p
+
+
+def test_particle_clocks_without_own_lengths_change_nothing():
+    """Clocks with dt_impl = dt and no end: the same states and flags as the
+    fixed-step push, and every clock is the running sum of dt."""
+    base = _c1_particles()
+    p1, p2 = base.copy(), _clocked(base)
+    P = O.push_params(0.0, 0.05, pusher=O.HYB2, thr=1e-15, r_min=2.0)
+    t = 0.0
+    for _ in range(12):
+        O.push(P, p1)
+        O.push(P, p2)
+        t += 0.05
+    assert np.array_equal(p1.state(), p2.state()) and np.array_equal(p1.flags, p2.flags)
+    assert np.all(p2.t[(p2.flags & O.ALIVE) != 0] == t)
+
+
+def test_each_scheme_advances_by_its_own_step():
+    """Table 2 pairs a Delta t_RK4 with a Delta t_Ham: a hybrid that always
+    accepts is RK4 at dt (clock n dt), one that always rejects is the
+    discrete-gradient scheme at dt_impl (clock n dt_impl), each checked
+    against the single-step routines called with that step; a mixed run
+    advances every clock by the step its scheme took."""
+    base = _c1_particles(16)
+    for thr, dt_used in ((np.inf, 0.5), (-np.inf, 1.0)):
+        p = _clocked(base)
+        P = O.push_params(0.0, 0.5, pusher=O.HYB2, thr=thr, r_min=2.0, dt_impl=1.0)
+        z = base.state()
+        for _ in range(3):
+            O.push(P, p)
+            for k in range(base.n):
+                Q = O.push_params(0.0, dt_used, r_min=2.0)
+                z[k] = O.step_rk4(Q, 0.0, z[k])[0] if thr > 0 else O.step_ham(Q, z[k])[0]
+        assert np.array_equal(p.state(), z)
+        assert np.all(p.t == 3 * dt_used)
+    p = _clocked(_c1_particles())
+    P = O.push_params(0.0, 0.5, pusher=O.HYB2, thr=1e-15, r_min=2.0, dt_impl=1.0)
+    for _ in range(6):
+        t0 = p.t.copy()
+        O.push(P, p)
+        alive = (p.flags & O.ALIVE) != 0
+        impl = (p.flags & O.IMPLICIT) != 0
+        assert np.all((p.t - t0)[alive & impl] == 1.0)
+        assert np.all((p.t - t0)[alive & ~impl] == 0.5)
+        assert impl[alive].any() and (~impl[alive]).any()
+
+
+def test_clocks_stop_exactly_at_t_end():
+    """With an end time the last step is clipped to the time left and lands
+    on t_end; afterwards the particles stay put.  The clipped explicit step
+    is RK4 with the remaining time as its step."""
+    p = _clocked(_c1_particles(32))
+    t_end = 2.3
+    P = O.push_params(0.0, 0.5, pusher=O.HYB2, thr=1e-15, r_min=2.0, dt_impl=1.0, t_end=t_end)
+    for _ in range(8):
+        before, t0 = p.copy(), p.t.copy()
+        O.push(P, p)
+        alive = (p.flags & O.ALIVE) != 0
+        last = alive & (t0 == 2.0) & ((p.flags & O.IMPLICIT) == 0)
+        for k in np.nonzero(last)[0]:
+            Q = O.push_params(0.0, t_end - 2.0, r_min=2.0)
+            assert np.array_equal(p.state()[k], O.step_rk4(Q, 0.0, before.state()[k])[0])
+    alive = (p.flags & O.ALIVE) != 0
+    assert np.all(p.t[alive] == t_end)
+    frozen = p.copy()
+    O.push(P, p)
+    assert np.array_equal(p.state(), frozen.state()) and np.array_equal(p.t, frozen.t)
+    assert np.all(p.flags[alive] == O.ALIVE) and np.all(p.iters == 0)
+
+
+def test_table2_hybrid_keeps_energy_in_a_tenth_of_the_steps():
+    """Sec. 3.1.2 with the a.0 row of Table 2: Hyb2 (Delta t_RK4 = 0.5,
+    Delta t_Ham = 1, threshold 1e-15) reaches t = 200 in at most 400 steps
+    per particle, against 4000 for RK4 at 0.05, with a worst energy
+    violation no larger than RK4's and at the 1e-14 level."""
+    T = 200.0
+    worst, steps = {}, {}
+    for name, pusher, dt, dt_impl, thr in (("rk4", O.RK4, 0.05, 0.0, 0.0),
+                                           ("hyb2", O.HYB2, 0.5, 1.0, 1e-15)):
+        p = _clocked(_c1_particles())
+        P = O.push_params(0.0, dt, pusher=pusher, thr=thr, r_min=2.0, dt_impl=dt_impl, t_end=T)
+        n = 0
+        while (p.t[(p.flags & O.ALIVE) != 0] < T).any():
+            O.push(P, p)
+            n += 1
+        alive = (p.flags & O.ALIVE) != 0
+        H = np.array([O.energy(0.0, z) for z in p.state()[alive]])
+        worst[name] = np.max(np.abs(H - p.H0[alive]) / np.abs(p.H0[alive]))
+        steps[name] = n
+    assert steps["rk4"] == 4000 and steps["hyb2"] <= 400
+    assert worst["hyb2"] <= worst["rk4"] and worst["hyb2"] < 1e-13
+
+
 # ----------------------------------------------------------------- gather
 def test_gather_exact_for_bilinear_densitized_fields():
     """The metric-weighted bilinear gather reproduces exactly any field
