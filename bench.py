@@ -248,6 +248,51 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
             "t_particle_s": t_part, "t_grid_s": t_grid}
 
 
+# the a.0 rows of Table 2 (Sec. 3.1.2): scheme, Delta t_RK4, Delta t_Ham, threshold
+TABLE2_A0 = (("RK4", "rk4", 0.05, 0.0, 0.0), ("Ham", "ham", 0.0, 1.0, 0.0),
+             ("Hyb1", "hyb1", 0.08, 1.0, 1.5), ("Hyb2", "hyb2", 0.5, 1.0, 1e-15))
+
+
+def table2_runs(G, W, t_end):
+    """The hybrid experiment of Sec. 3.1.2 on the test-particle workload:
+    every scheme of the a.0 rows of Table 2 with its own step lengths, each
+    particle run on its own clock to t_end.  Reports the wall time, the
+    particle-steps taken and the energy violation |H - H0|/H0 at t_end."""
+    pushers = {"rk4": G.PUSH_RK4, "ham": G.PUSH_HAM, "hyb1": G.PUSH_HYB1,
+               "hyb2": G.PUSH_HYB2}
+    n = W["n"]
+    out = {"t_end": t_end, "particles": n, "schemes": {}}
+    for name, key, dt_rk, dt_ham, thr in TABLE2_A0:
+        dt = dt_rk if dt_rk > 0 else dt_ham
+        cfg = G.config_default(a=W["a"], dt=dt, dt_implicit=dt_ham, t_end=t_end,
+                               pusher=pushers[key], hyb_threshold=thr, max_particles=n,
+                               r_remove_in=rplus(W["a"]))
+        with G.Context(cfg) as ctx:
+            ctx.init_particles(G.INIT_ORBITS, n, SEED + 1, 6.0, 20.0, np.pi / 4,
+                               3 * np.pi / 4, W["theta"])
+            # enough steps for the clock that only takes the shorter step
+            nsteps = int(np.ceil(t_end / min(dt, dt_ham if dt_ham > 0 else dt))) + 1
+            ctx.sync()
+            t0 = time.perf_counter()
+            ctx.step(nsteps)
+            ctx.sync()
+            wall = time.perf_counter() - t0
+            d = ctx.diagnostics()
+            P = ctx.get_particles()
+            t = ctx.get_times()
+        alive = (P["flags"] & G.FLAG_ALIVE) != 0
+        assert np.all(t[alive] == t_end)
+        h = P["herr"][alive]
+        out["schemes"][name] = {
+            "dt_rk4": dt_rk or None, "dt_ham": dt_ham or None, "threshold": thr or None,
+            "launches": nsteps, "wall_s": wall, "implicit_particle_steps": int(d["implicit_steps"]),
+            "herr_max": float(h.max()), "herr_median": float(np.median(h)),
+            "alive": int(alive.sum())}
+        print(f"[bench] Table 2 {name}: {wall:.3f} s, |H-H0|/H0 max {h.max():.2e} "
+              f"median {np.median(h):.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
     """The charged test-particle workload (Kerr a=0.9, Wald field on 512^2,
     2^20 particles) with the implicit midpoint pusher on every particle,
@@ -347,6 +392,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain guess comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--table2-t", type=float, default=1000.0,
+                    help="end time of the Table 2 scheme runs (workload c1; 0 skips them)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scale)")
     args = ap.parse_args()
@@ -459,6 +506,9 @@ def main():
                                       if v[1] > 0}
 
     ctx.close()
+    table2 = None
+    if args.workload == "c1" and args.table2_t > 0:
+        table2 = table2_runs(G, W, args.table2_t)
     learned = None
     if not args.no_learned:
         print("[bench] learned vs plain implicit guess", file=sys.stderr, flush=True)
@@ -492,6 +542,7 @@ def main():
         "autotune": tune,
         "learned_guess_training": mlp_info,
         "learned_guess": learned,
+        "table2_a0": table2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

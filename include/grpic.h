@@ -120,6 +120,13 @@ typedef struct grpic_config {
   int push_waves_per_simd; /* register budget of the explicit push: 0 = the
                               compiler's choice, 4 = at most 128 VGPRs so that
                               4 waves fit per SIMD (set by grpic_autotune)  */
+  /* Steps of their own length (Sec. 3.1.2, Table 2), field_mode NONE only:
+   * every particle keeps its own time; the explicit RK4 trial advances it by
+   * dt, the implicit scheme by dt_implicit; with t_end > 0 both are clipped
+   * to the time left (a clipped step lands on t_end exactly) and particles
+   * that reached t_end are no longer advanced (flags ALIVE, iters 0).     */
+  double dt_implicit;    /* step of the implicit scheme (0: dt)            */
+  double t_end;          /* end time of the particle clocks (0: none)      */
 } grpic_config;
 
 /* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */
@@ -207,6 +214,9 @@ int grpic_get_particles(grpic_ctx *ctx, long n, double *r, double *th,
                         double *qm, double *w, double *H0, double *herr,
                         int32_t *flags, int32_t *iters);
 int grpic_num_particles(grpic_ctx *ctx, long *n);
+/* Copy the particles' own times (field_mode NONE) in id order into t[n];
+ * they start at 0 when particles are loaded.  GRPIC_E_STATE with a grid. */
+int grpic_get_times(grpic_ctx *ctx, long n, double *t);
 /* Copy the particles with the given ids (m <= 2^24 distinct ids in
  * [0, n)): rec receives 10 doubles per id (r, theta, phi, u_r, u_theta,
  * u_phi, q/m, w, H0, herr), flags and iters (may be NULL) one int each.
@@ -224,7 +234,8 @@ int grpic_sample_particles(grpic_ctx *ctx, long m, const long *ids,
  * storage order (r, theta, phi, u_r, u_theta, u_phi, H0, herr, w as FP64;
  * q/m as int8; flags, iters as uint8; id as uint32; with a grid the
  * deposit weights W1..W3 of the current position as FP64 and the cell
- * index as int32), then the diagnostic counters.  Restoring it into a
+ * index as int32; without a grid the particle times as FP64), then the
+ * diagnostic counters.  Restoring it into a
  * context of the same grid, field mode and dt continues the run exactly as
  * the uninterrupted one (the deposit sums are order-independent).  The
  * learned-guess network is not part of it (grpic_mlp_get / grpic_mlp_set). */

@@ -45,7 +45,8 @@ class Config(C.Structure):
                 ("reflect", C.c_int), ("max_particles", C.c_long),
                 ("sort_every", C.c_int), ("tile_r", C.c_int), ("tile_th", C.c_int),
                 ("block", C.c_int), ("persistent_waves", C.c_int),
-                ("push_waves_per_simd", C.c_int)]
+                ("push_waves_per_simd", C.c_int), ("dt_implicit", C.c_double),
+                ("t_end", C.c_double)]
 
 
 class InitSpec(C.Structure):
@@ -224,6 +225,13 @@ class Context:
         out["flags"], out["iters"] = flags, iters
         out["z"] = np.stack([out[k] for k in ("r", "th", "ph", "ur", "uth", "uph")], axis=1)
         return out
+
+    def get_times(self):
+        """Each particle's own time (no grid), in id order."""
+        n = self.num_particles()
+        t = np.zeros(n)
+        self._c("grpic_get_times", C.c_long(n), _dp(t))
+        return t
 
     def sample_particles(self, ids):
         """Particle records of the given ids, as get_particles() returns them."""

@@ -91,6 +91,15 @@ void validate(const grpic_config& c) {
       bad("too many sort tiles (at most 16384): enlarge tile_r / tile_th");
     if (c.dt < 0.0) bad("dt must be positive with a grid");
   }
+  if (!(c.dt_implicit >= 0.0 && std::isfinite(c.dt_implicit)))
+    bad("dt_implicit must be finite and >= 0");
+  if (!(c.t_end >= 0.0 && std::isfinite(c.t_end))) bad("t_end must be finite and >= 0");
+  if ((c.dt_implicit > 0.0 && c.dt_implicit != c.dt) || c.t_end > 0.0) {
+    if (c.field_mode != GRPIC_FIELDS_NONE)
+      bad("steps of their own length and t_end need field_mode NONE");
+    if (!(c.dt > 0.0)) bad("steps of their own length need dt > 0");
+    if (c.guess == GRPIC_GUESS_MLP) bad("the learned guess needs one common dt");
+  }
 }
 
 void alloc_particles(grpic_ctx* c, long cap) {
@@ -123,6 +132,7 @@ void alloc_particles(grpic_ctx* c, long cap) {
   P.th_old = evolve ? dalloc<double>(n) : nullptr;
   P.dphi = evolve ? dalloc<double>(n) : nullptr;
   c->xqueue = evolve ? dalloc<int>(n) : nullptr;
+  P.t = c->cfg.field_mode == GRPIC_FIELDS_NONE ? dalloc<double>(n) : nullptr;
   if (c->cfg.pusher != GRPIC_PUSH_RK4) {
     // explicit-pass block b appends to segment b % kQueueSegs, so a segment
     // holds at most ceil(blocks / kQueueSegs) blocks of 256 entries
@@ -160,6 +170,7 @@ void free_particles(grpic_ctx* c) {
     dfree(V->r_old);
     dfree(V->th_old);
     dfree(V->dphi);
+    dfree(V->t);
   }
   dfree(c->queue);
   dfree(c->xqueue);
@@ -315,6 +326,7 @@ void particles_loaded(grpic_ctx* c) {
   drop_graphs(c);
   launch_fill(c, c->stats, sizeof(Stats));
   c->steps = 0;
+  if (c->pv.t && c->n > 0) launch_fill(c, c->pv.t, sizeof(double) * (size_t)c->n);
   if (c->cfg.field_mode == GRPIC_FIELDS_NONE) return;
   launch_sort(c);
   if (c->cfg.field_mode == GRPIC_FIELDS_EVOLVE) {
@@ -827,6 +839,22 @@ int grpic_num_particles(grpic_ctx* c, long* n) {
   });
 }
 
+int grpic_get_times(grpic_ctx* c, long n, double* t) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!c->pv.t) throw Error(GRPIC_E_STATE, "particle clocks exist only without a grid");
+    if (n != c->n) throw Error(GRPIC_E_INVALID, "n differs from the particle count");
+    if (n > 0 && !t) throw Error(GRPIC_E_INVALID, "null host buffer");
+    GRPIC_HIP(hipStreamSynchronize(c->stream));
+    if (n == 0) return;
+    std::vector<uint32_t> id(n);
+    std::vector<double> tmp(n);
+    GRPIC_HIP(hipMemcpy(id.data(), c->pv.id, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    GRPIC_HIP(hipMemcpy(tmp.data(), c->pv.t, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (long k = 0; k < n; ++k) t[id[k]] = tmp[k];
+  });
+}
+
 int grpic_get_particles(grpic_ctx* c, long n, double* r, double* th,
                         double* ph, double* ur, double* uth, double* uph,
                         double* qm, double* w, double* H0, double* herr,
@@ -1180,6 +1208,7 @@ std::vector<StateItem> state_items(grpic_ctx* c, long n) {
     for (int q = 1; q < 4; ++q) v.push_back({P.W[q], d});
     v.push_back({P.cell, sizeof(int) * (size_t)n});
   }
+  if (P.t) v.push_back({P.t, d});
   v.push_back({c->stats, sizeof(Stats)});
   return v;
 }

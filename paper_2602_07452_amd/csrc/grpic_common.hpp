@@ -30,6 +30,7 @@ struct ParticleView {
   double* Wn[4];                         // the same at the pushed position
   int* celln;
   double *r_old, *th_old, *dphi;         // previous position, phi change
+  double* t;                             // own time (field mode NONE only)
 };
 
 // device counters written by the particle kernels.  Counters that many

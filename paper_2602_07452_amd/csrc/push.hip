@@ -30,6 +30,7 @@ struct PushArgs {
   FieldView f;
   ParticleView p;
   double a, dt, thr, tol, ham_eps, r_min, r_max, th_lo, th_hi;
+  double dt_im, t_end;  // implicit step and clock end (no grid only)
   int pusher, guess, kmax, reflect;
   double* gz[6];
   int* queue;       // kQueueSegs segments of seg_cap entries
@@ -143,10 +144,10 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
 // classical RK4 with the fields re-gathered at every stage; s0, c0 (out):
 // sin, cos of z[1], from which the stage angles are reached by short series
 template <bool GRID>
-__device__ __forceinline__ void rk4(const PushArgs& A, double qm,
+__device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
                                     const double* z, double* out, double* Wq,
                                     double* e0, double* s0, double* c0) {
-  const double dt = A.dt, hdt = 0.5 * A.dt;
+  const double hdt = 0.5 * dt;
   double k[6], acc[6], y[6], p, pacc, s, c;
   fsincos(z[1], s0, c0);
   eval<GRID>(A, qm, z, *s0, *c0, k, &p, e0);
@@ -193,8 +194,8 @@ __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
 
 // implicit midpoint rule by fixed-point iteration; zk: guess in, result out
 template <bool GRID>
-__device__ int imr(const PushArgs& A, double qm, const double* z, double s0, double c0,
-                   double* zk, double* Wq) {
+__device__ int imr(const PushArgs& A, double dt, double qm, const double* z, double s0,
+                   double c0, double* zk, double* Wq) {
   double p = 0.0;
   for (int k = 1; k <= A.kmax; ++k) {
     double zm[6], f[6], zn[6], sm, cm;
@@ -203,16 +204,16 @@ __device__ int imr(const PushArgs& A, double qm, const double* z, double s0, dou
     sincos_near(zm[1], z[1], s0, c0, &sm, &cm);
     eval<GRID>(A, qm, zm, sm, cm, f, &p);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) zn[i] = z[i] + A.dt * f[i];
+    for (int i = 0; i < 6; ++i) zn[i] = z[i] + dt * f[i];
     bool c = small_change(zn, zk, A.tol);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zk[i] = zn[i];
     if (c) {
-      *Wq = A.dt * p;
+      *Wq = dt * p;
       return k;
     }
   }
-  *Wq = A.dt * p;
+  *Wq = dt * p;
   return -A.kmax;
 }
 
@@ -233,7 +234,7 @@ __device__ __forceinline__ double lorentz(const Met& m, double ur, double ut,
               2.0 * m.irp * ur * up);
 }
 
-__device__ int ham_dg(const PushArgs& A, const double* z, double* zk) {
+__device__ int ham_dg(const PushArgs& A, double dt, const double* z, double* zk) {
   for (int k = 1; k <= A.kmax; ++k) {
     Met M[4];  // index: bit0 = r updated, bit1 = theta updated
     metric(A.a, z[0], z[1], M[0]);
@@ -302,12 +303,12 @@ __device__ int ham_dg(const PushArgs& A, const double* z, double* zk) {
       }
     }
     double zn[6];
-    zn[0] = z[0] + A.dt * grad[3];
-    zn[1] = z[1] + A.dt * grad[4];
-    zn[2] = z[2] + A.dt * grad[5];
-    zn[3] = z[3] - A.dt * grad[0];
-    zn[4] = z[4] - A.dt * grad[1];
-    zn[5] = z[5] - A.dt * grad[2];
+    zn[0] = z[0] + dt * grad[3];
+    zn[1] = z[1] + dt * grad[4];
+    zn[2] = z[2] + dt * grad[5];
+    zn[3] = z[3] - dt * grad[0];
+    zn[4] = z[4] - dt * grad[1];
+    zn[5] = z[5] - dt * grad[2];
     bool c = small_change(zn, zk, A.tol);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zk[i] = zn[i];
@@ -424,25 +425,48 @@ void k_push_explicit(PushArgs A) {
     double z[6];
     load_z(P, k, z);
     double qm = (double)P.qm[k];
-    if (A.pusher == GRPIC_PUSH_IMR || A.pusher == GRPIC_PUSH_HAM) {
+    // without a grid each particle keeps its own time: the step is clipped
+    // to the time left before t_end, and a particle at t_end stays
+    double dt = A.dt, tk = 0.0;
+    bool frozen = false, ends = false;
+    if constexpr (!GRID) {
+      tk = P.t[k];
+      if (A.t_end > 0.0) {
+        double left = A.t_end - tk;
+        if (!(left > 0.0)) {
+          frozen = true;
+        } else if (left <= dt) {
+          dt = left;
+          ends = true;
+        }
+      }
+    }
+    if (frozen) {
+      P.flags[k] = F_ALIVE;
+      P.iters[k] = 0;
+      atomicAdd(&ls.alive, 1u);
+      atomicAdd(&ls.herr_hist[herr_bin(P.herr[k])], 1u);
+    } else if (A.pusher == GRPIC_PUSH_IMR || A.pusher == GRPIC_PUSH_HAM) {
       enq = true;
 #pragma unroll
       for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
     } else {
       double Wq, e0, s0, c0;
-      rk4<GRID>(A, qm, z, trial, &Wq, &e0, &s0, &c0);
+      rk4<GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0);
       double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
         accept = v < A.thr;
       } else if (A.pusher == GRPIC_PUSH_HYB1) {
         double prev = P.herr[k];
-        accept = (v - prev) / (A.dt * fmax(prev, 0x1p-52)) < A.thr;
+        accept = (v - prev) / (dt * fmax(prev, 0x1p-52)) < A.thr;
       }
-      if (accept)
+      if (accept) {
         finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0);
-      else
+        if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
+      } else {
         enq = true;
+      }
     }
   }
   // append the rejected particles to the implicit queue: wave ballots, one
@@ -509,14 +533,25 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         for (int i = 0; i < 6; ++i) zk[i] = A.gz[i][slot];
       }
       const bool ham = HAM && qm == 0.0 && A.pusher != GRPIC_PUSH_IMR;
+      // the implicit step (no grid: its own length, clipped before t_end)
+      double dt = A.dt, tk = 0.0;
+      bool ends = false;
+      if constexpr (!GRID) {
+        dt = A.dt_im;
+        tk = P.t[k];
+        if (A.t_end > 0.0 && A.t_end - tk <= dt) {
+          dt = A.t_end - tk;
+          ends = true;
+        }
+      }
       double Wq = 0.0, s0, c0;
       fsincos(z[1], &s0, &c0);
-      int it = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, s0, c0, zk, &Wq);
+      int it = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
       if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
         // no convergence from the learned guess: restart from z^n
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = z[i];
-        int it2 = ham ? ham_dg(A, z, zk) : imr<GRID>(A, qm, z, s0, c0, zk, &Wq);
+        int it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
         it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
       }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
@@ -535,6 +570,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       double e0 = qm != 0.0 ? energy_sc(A.a, z, s0, c0) : 0.0;
       double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0);
       finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0);
+      if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
     }
   }
   __syncthreads();
@@ -568,6 +604,8 @@ static PushArgs make_args(grpic_ctx* c) {
   A.p.n = c->n;
   A.a = c->cfg.a;
   A.dt = c->cfg.dt;
+  A.dt_im = c->cfg.dt_implicit > 0.0 ? c->cfg.dt_implicit : c->cfg.dt;
+  A.t_end = c->cfg.t_end;
   A.thr = c->cfg.hyb_threshold;
   A.tol = c->cfg.tol;
   A.ham_eps = c->cfg.ham_eps;

@@ -58,14 +58,17 @@ def push_params_from(cfg, field_kind):
                          r_max=cfg.r_remove_out,
                          th_lo=cfg.theta0 if cfg.reflect else -1.0,
                          th_hi=np.pi - cfg.theta0 if cfg.reflect else 10.0,
-                         ham_eps=cfg.ham_eps)
+                         ham_eps=cfg.ham_eps, dt_impl=cfg.dt_implicit, t_end=cfg.t_end)
 
 
-def compare_push(cfg, before, after, P, grid=None, G6=None, tol=TOL_STATE):
-    """Run the oracle push from `before` (GPU particle dict) and compare with
-    the GPU result `after`.  Hybrid decisions inside the tie band are
-    re-run in the oracle with the GPU's choice.  Returns the max error."""
+def compare_push(cfg, before, after, P, grid=None, G6=None, tol=TOL_STATE, t=None):
+    """Run the oracle push from `before` (GPU particle dict; t: the particle
+    clocks before the step, if any) and compare with the GPU result `after`.
+    Hybrid decisions inside the tie band are re-run in the oracle with the
+    GPU's choice.  Returns the max error and the oracle's particles."""
     p = oracle_particles(before)
+    if t is not None:
+        p.t = np.array(t, np.float64)
     O.push(P, p, grid=grid, G=G6)
     gpu_impl = (after["flags"] & G.FLAG_IMPLICIT) != 0
     orc_impl = (p.flags & O.IMPLICIT) != 0
@@ -81,6 +84,8 @@ def compare_push(cfg, before, after, P, grid=None, G6=None, tol=TOL_STATE):
         force = np.full(len(before["r"]), -1, np.int32)
         force[mismatch] = gpu_impl[mismatch].astype(np.int32)
         p = oracle_particles(before)
+        if t is not None:
+            p.t = np.array(t, np.float64)
         O.push(P, p, grid=grid, G=G6, force=force)
     alive = (before["flags"] & 1) != 0
     err = state_err(after["z"][alive], p.state()[alive])

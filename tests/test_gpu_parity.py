@@ -50,6 +50,49 @@ def test_neutral_pushers_one_step(orbits, pusher, thr):
     assert err <= TOL_STATE
 
 
+@pytest.mark.parametrize("pusher,dt,dt_im,thr,t_end", [
+    (G.PUSH_HYB2, 0.5, 1.0, 1e-15, 4.3),   # Table 2, a.0 row
+    (G.PUSH_HYB1, 0.08, 1.0, 1.5, 1.0),    # Table 2, a.0 row
+    (G.PUSH_HAM, 1.0, 1.0, 0.0, 3.5)])
+def test_own_step_lengths_match_oracle(orbits, pusher, dt, dt_im, thr, t_end):
+    """Steps of their own length (Sec. 3.1.2, Table 2): every step of the
+    run to t_end against the oracle from the GPU's state and clocks; the
+    clocks agree bit for bit, the clipped last steps land on t_end, and the
+    particles then stay."""
+    cfg0, P0 = orbits
+    cfg = G.config_default(a=0.0, dt=dt, dt_implicit=dt_im, t_end=t_end,
+                           max_particles=len(P0["r"]), pusher=pusher, hyb_threshold=thr,
+                           r_remove_in=2.0)
+    Pp = push_params_from(cfg, O.FIELDS_NONE)
+    impl = expl = 0
+    with G.Context(cfg) as ctx:
+        ctx.load_particles(P0["z"], P0["qm"], P0["w"], H0=P0["H0"])
+        assert np.all(ctx.get_times() == 0.0)
+        for _ in range(100):
+            before, t0 = ctx.get_particles(), ctx.get_times()
+            alive = (before["flags"] & 1) != 0
+            if np.all(t0[alive] == t_end):
+                break
+            ctx.step(1)
+            after, t1 = ctx.get_particles(), ctx.get_times()
+            _, p = compare_push(cfg, before, after, Pp, t=t0)
+            assert np.array_equal(t1[alive], p.t[alive])
+            moved = alive & (t0 < t_end)
+            step_impl = (after["flags"] & G.FLAG_IMPLICIT) != 0
+            impl += int((moved & step_impl).sum())
+            expl += int((moved & ~step_impl).sum())
+        else:
+            raise AssertionError("clocks did not reach t_end")
+        ctx.step(1)
+        still = ctx.get_particles()
+        assert np.array_equal(still["z"][alive], before["z"][alive])
+        assert np.all(still["flags"][alive] == G.FLAG_ALIVE)
+        assert np.all(still["iters"][alive] == 0)
+        assert ctx.diagnostics()["alive"] == int(alive.sum())
+    if pusher != G.PUSH_HAM:
+        assert impl > 0 and expl > 0
+
+
 def test_neutral_hybrid_many_steps_statistics(orbits):
     """40 Hyb2 steps at the a = 0 Table 2 threshold (1e-15, at the rounding
     level of the switch value, so individual choices are ties): the GPU keeps
