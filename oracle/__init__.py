@@ -26,6 +26,7 @@ I_P = C.POINTER(C.c_int)
 RK4, IMR, HAM, HYB1, HYB2 = 0, 1, 2, 3, 4
 GUESS_PLAIN, GUESS_RK4, GUESS_EXTERNAL = 0, 1, 2
 FIELDS_NONE, FIELDS_GRID, FIELDS_WALD = 0, 1, 2
+DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
 ALIVE, IMPLICIT, NOCONV, REMOVED, REFLECTED = 1, 2, 4, 8, 16
 NPARAM = 5510
 
@@ -36,15 +37,16 @@ class PushParams(C.Structure):
                 ("kmax", C.c_int), ("field_kind", C.c_int), ("B0", C.c_double),
                 ("r_min", C.c_double), ("r_max", C.c_double),
                 ("th_lo", C.c_double), ("th_hi", C.c_double),
-                ("ham_eps", C.c_double), ("dt_impl", C.c_double), ("t_end", C.c_double)]
+                ("ham_eps", C.c_double), ("dt_impl", C.c_double), ("t_end", C.c_double),
+                ("deposit_mode", C.c_int)]
 
 
 def push_params(a, dt, pusher=RK4, guess=GUESS_PLAIN, thr=0.0, tol=1e-13,
                 kmax=50, field_kind=FIELDS_NONE, B0=0.0, r_min=0.0,
                 r_max=1e300, th_lo=-1.0, th_hi=10.0, ham_eps=1e-10, dt_impl=0.0,
-                t_end=0.0):
+                t_end=0.0, deposit_mode=DEPOSIT_CONSERVING):
     return PushParams(a, dt, pusher, guess, thr, tol, kmax, field_kind, B0,
-                      r_min, r_max, th_lo, th_hi, ham_eps, dt_impl, t_end)
+                      r_min, r_max, th_lo, th_hi, ham_eps, dt_impl, t_end, deposit_mode)
 
 
 class _OmParticles(C.Structure):
@@ -400,6 +402,28 @@ def pic_step(P, grid, F, particles=None, absorber=None, guess=None,
 
 
 # -------------------------------------------------------------- diagnostics
+def deposit_paper(grid, z, qw, mode=None):
+    """The paper's current (Sec. 2.3) at the states z (n,6): densitized
+    (rho, J^r, J^theta, J^phi) on their sub-grids."""
+    z, qw = _f64(np.atleast_2d(z)), _f64(qw)
+    n = z.shape[0]
+    mode = np.ones(n, np.int32) if mode is None else np.ascontiguousarray(mode, np.int32)
+    rho, Jr, Jt, Jp = grid.zeros(6), grid.zeros(0), grid.zeros(1), grid.zeros(6)
+    cols = [np.ascontiguousarray(z[:, i]) for i in (0, 1, 3, 4, 5)]
+    lib().om_deposit_paper(grid.h, C.c_long(n), *[_p(c) for c in cols], _p(qw), _ip(mode),
+                           _p(rho), _p(Jr), _p(Jt), _p(Jp))
+    return rho, Jr, Jt, Jp
+
+
+def div_clean(grid, D, rho_d, iters):
+    """Divergence cleaning (Sec. 2.4): returns the corrected copies of the
+    plain D^i and phi at the nodes."""
+    Dc = [_f64(x).copy() for x in D]
+    phi = grid.zeros(6)
+    lib().om_div_clean(grid.h, _ptrs(Dc), _p(_f64(rho_d)), C.c_int(iters), _p(phi))
+    return Dc, phi
+
+
 def gauss_residual(grid, D, rho_d):
     out = grid.zeros(6)
     lib().om_gauss_residual(grid.h, _ptrs([_f64(x) for x in D]),

@@ -82,6 +82,7 @@ void om_gather(const om_grid *g, const double *const *G, double r, double th,
 enum { OM_RK4 = 0, OM_IMR = 1, OM_HAM = 2, OM_HYB1 = 3, OM_HYB2 = 4 };
 enum { OM_GUESS_PLAIN = 0, OM_GUESS_RK4 = 1, OM_GUESS_EXTERNAL = 2 };
 enum { OM_FIELDS_NONE = 0, OM_FIELDS_GRID = 1, OM_FIELDS_WALD = 2 };
+enum { OM_DEPOSIT_CONSERVING = 0, OM_DEPOSIT_PAPER = 1 };
 enum {
   OM_ALIVE = 1,
   OM_IMPLICIT = 2,
@@ -105,6 +106,7 @@ typedef struct {
                        Delta t_RK4 with a larger Delta t_Ham               */
   double t_end;     /* with particle clocks: steps are clipped to end at
                        t_end and particles that reached it stay (0: none) */
+  int deposit_mode; /* OM_DEPOSIT_CONSERVING or OM_DEPOSIT_PAPER (pic step) */
 } om_push_params;
 
 typedef struct {
@@ -151,6 +153,17 @@ void om_deposit(const om_grid *g, double dt, long n, const double *r0,
                 const double *th1, const double *ph1, const double *qw,
                 const int *mode, double *rho, double *Jr, double *Jth,
                 double *Jph);
+/* the paper's own current (Sec. 2.3) at the pushed state, every component
+ * on its own Yee subgrid; densitized like om_deposit (adds to the arrays)  */
+void om_deposit_paper(const om_grid *g, long n, const double *r,
+                      const double *th, const double *ur, const double *uth,
+                      const double *uph, const double *qw, const int *mode,
+                      double *rho, double *Jr, double *Jth, double *Jph);
+/* divergence cleaning (Sec. 2.4, eq. phi): `iters` Jacobi sweeps from phi = 0
+ * on the Gauss residual of D (plain values, corrected in place) and the
+ * densitized rho; phi_out (nodes, may be NULL) receives phi              */
+void om_div_clean(const om_grid *g, double *const *D, const double *rho_d,
+                  int iters, double *phi_out);
 
 /* ---- Maxwell solver (Sec. 2.1) ------------------------------------------*/
 /* non-densitized D^i, B^i; E_i, H_i are grid fields at their Yee points    */

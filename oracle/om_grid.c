@@ -14,6 +14,9 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* component arrays: r fastest, index j nR + i                               */
+#define IDX(nR, i, j) ((long)(j) * (nR) + (i))
+
 /* ------------------------------------------------------------------------
  * Grid: r log-spaced between r_in and r_out, theta uniform on
  * [theta0, pi - theta0] (half-theta domain, Sec. 2.5); half radii are the
@@ -152,6 +155,20 @@ static double subvol(double a, int flat, double r0, double r1, double t0,
       sum += cw[i] * cw[j] * f;
     }
   return hr * ht * sum;
+}
+
+/* weights of the corners (ra,ta), (rb,ta), (ra,tb), (rb,tb) of any cell  */
+static void box_weights(double a, int flat, double r, double th, double ra,
+                        double rb, double ta, double tb, double *W) {
+  double V00 = subvol(a, flat, ra, r, ta, th);
+  double V10 = subvol(a, flat, r, rb, ta, th);
+  double V01 = subvol(a, flat, ra, r, th, tb);
+  double V11 = subvol(a, flat, r, rb, th, tb);
+  double V = V00 + V10 + V01 + V11;
+  W[0] = V11 / V;
+  W[1] = V01 / V;
+  W[2] = V10 / V;
+  W[3] = V00 / V;
 }
 
 void om_dep_weights(const om_grid *g, double r, double th, int p, int q,
@@ -361,6 +378,150 @@ void om_deposit(const om_grid *g, double dt, long n, const double *r0,
 }
 
 /* ------------------------------------------------------------------------
+ * The paper's own current (Sec. 2.3), a deposit mode of its own.  Every
+ * particle alive after the push deposits at its new position x^{n+2} with
+ * u^{n+2}: rho with the node weights, each current component on its own Yee
+ * subgrid (J^r at (r_{i+1/2}, theta_j), J^theta at (r_i, theta_{j+1/2}),
+ * J^phi at the nodes) with the volume weights of that subgrid's cell, each
+ * carried by the coordinate velocity dx^i/dt = alpha v^i - beta^i of eq. p1.
+ * The sums of the paper give the FIDO current j; q w (alpha v - beta) is the
+ * grid current J = alpha j - rho beta that eq. m3 needs (reading).  A
+ * position outside a half subgrid's range (below r_{1/2}, above
+ * r_{N-1/2}, or within half a cell of a theta edge) is moved onto its edge
+ * for that component.  Densitized values: sqrt(g) rho = Q / (2 pi Lr Lt),
+ * sqrt(g) J^r = sum q w W dr/dt / (2 pi (r_{i+1} - r_i) Lt_j), sqrt(g)
+ * J^theta = sum q w W dth/dt / (2 pi Lr_i dth), sqrt(g) J^phi = sum q w W
+ * dphi/dt / (2 pi Lr Lt).  Not charge-conserving: Gauss's law is restored
+ * by cleaning (om_div_clean).
+ * ------------------------------------------------------------------------ */
+static double clampd(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+void om_deposit_paper(const om_grid *g, long n, const double *r,
+                      const double *th, const double *ur, const double *uth,
+                      const double *uph, const double *qw, const int *mode,
+                      double *rho, double *Jr, double *Jth, double *Jph) {
+  int nr = g->nr, nth = g->nth, nrn = nr + 1, ntn = nth + 1;
+  double tp = 2.0 * M_PI;
+  for (long k = 0; k < n; ++k) {
+    if (!mode[k]) continue;
+    double z[6] = {r[k], th[k], 0.0, ur[k], uth[k], uph[k]};
+    double f[6], zero[3] = {0.0, 0.0, 0.0};
+    om_rhs(g->a, 0.0, z, zero, zero, f); /* f[0..2] = dx^i/dt, eq. p1   */
+    double W[4];
+    int p, q;
+    /* rho and J^phi at the nodes                                          */
+    node_cell(g, z[0], z[1], &p, &q);
+    om_dep_weights(g, z[0], z[1], p, q, 0, W);
+    for (int c = 0; c < 4; ++c) {
+      int i = p + (c & 1), j = q + (c >> 1);
+      double L = tp * Lr(g, i) * Lt(g, j);
+      rho[IDX(nrn, i, j)] += qw[k] * W[c] / L;
+      Jph[IDX(nrn, i, j)] += qw[k] * W[c] * f[2] / L;
+    }
+    /* J^r on (r_{i+1/2}, theta_j)                                          */
+    {
+      double rc = clampd(z[0], g->rh[0], g->rh[nr - 1]);
+      int pr = locate(g->rh, nr, rc);
+      box_weights(g->a, 0, rc, z[1], g->rh[pr], g->rh[pr + 1], g->tn[q],
+                  g->tn[q + 1], W);
+      for (int c = 0; c < 4; ++c) {
+        int i = pr + (c & 1), j = q + (c >> 1);
+        double L = tp * (g->rn[i + 1] - g->rn[i]) * Lt(g, j);
+        Jr[IDX(nr, i, j)] += qw[k] * W[c] * f[0] / L;
+      }
+    }
+    /* J^theta on (r_i, theta_{j+1/2})                                      */
+    {
+      double tc = clampd(z[1], g->th[0], g->th[nth - 1]);
+      int qt = locate(g->th, nth, tc);
+      box_weights(g->a, 0, z[0], tc, g->rn[p], g->rn[p + 1], g->th[qt],
+                  g->th[qt + 1], W);
+      for (int c = 0; c < 4; ++c) {
+        int i = p + (c & 1), j = qt + (c >> 1);
+        double L = tp * Lr(g, i) * g->dth;
+        Jth[IDX(nrn, i, j)] += qw[k] * W[c] * f[1] / L;
+      }
+    }
+  }
+  (void)ntn;
+}
+
+/* ------------------------------------------------------------------------
+ * Divergence cleaning (Sec. 2.4, eq. phi) in densitized form on the nodes:
+ *   d_r(sqrt(g) g^rr d_r phi) + d_th(sqrt(g) g^thth d_th phi) = G,
+ * G the Gauss residual div_h(sqrt(g) D) - 4 pi sqrt(g) rho of
+ * om_gauss_residual at the interior nodes (d_phi = 0, and g^rth = 0).
+ * d_r phi lives at (r_{i+1/2}, theta_j), d_th phi at (r_i, theta_{j+1/2}),
+ * where D^r and D^theta do, so the discrete operator is the discrete
+ * divergence of the discrete gradient.  phi = 0 on the boundary nodes
+ * (reading); phi starts at 0 and takes `iters` Jacobi sweeps; then
+ * D^i -= g^ij d_j phi (D^phi with g^phir and the mean of the two radial
+ * differences at interior nodes).
+ * ------------------------------------------------------------------------ */
+static double *dup0(long n) { return (double *)calloc(n, sizeof(double)); }
+
+static double gupper(const om_grid *g, double r, double th, int which) {
+  double m[13];
+  om_metric(g->a, r, th, m);
+  return m[which];
+}
+
+void om_div_clean(const om_grid *g, double *const *D, const double *rho_d,
+                  int iters, double *phi_out) {
+  int nr = g->nr, nth = g->nth, nrn = nr + 1, ntn = nth + 1;
+  long nn = (long)nrn * ntn;
+  double *G = dup0(nn), *phi = dup0(nn), *nxt = dup0(nn);
+  om_gauss_residual(g, (const double *const *)D, rho_d, G);
+  double dth = g->dth;
+  for (int it = 0; it < iters; ++it) {
+    for (int j = 1; j < nth; ++j)
+      for (int i = 1; i < nr; ++i) {
+        double Lri = g->rh[i] - g->rh[i - 1];
+        double aE = om_sqrtg(g->a, g->rh[i], g->tn[j]) *
+                    gupper(g, g->rh[i], g->tn[j], 6) /
+                    (g->rn[i + 1] - g->rn[i]) / Lri;
+        double aW = om_sqrtg(g->a, g->rh[i - 1], g->tn[j]) *
+                    gupper(g, g->rh[i - 1], g->tn[j], 6) /
+                    (g->rn[i] - g->rn[i - 1]) / Lri;
+        double aN = om_sqrtg(g->a, g->rn[i], g->th[j]) *
+                    gupper(g, g->rn[i], g->th[j], 7) / (dth * dth);
+        double aS = om_sqrtg(g->a, g->rn[i], g->th[j - 1]) *
+                    gupper(g, g->rn[i], g->th[j - 1], 7) / (dth * dth);
+        double nb = aE * phi[IDX(nrn, i + 1, j)] + aW * phi[IDX(nrn, i - 1, j)] +
+                    aN * phi[IDX(nrn, i, j + 1)] + aS * phi[IDX(nrn, i, j - 1)];
+        nxt[IDX(nrn, i, j)] = (nb - G[IDX(nrn, i, j)]) / (aE + aW + aN + aS);
+      }
+    double *t = phi;
+    phi = nxt;
+    nxt = t;
+  }
+  for (int j = 0; j <= nth; ++j)
+    for (int i = 0; i < nr; ++i)
+      D[0][IDX(nr, i, j)] -= gupper(g, g->rh[i], g->tn[j], 6) *
+                             (phi[IDX(nrn, i + 1, j)] - phi[IDX(nrn, i, j)]) /
+                             (g->rn[i + 1] - g->rn[i]);
+  for (int j = 0; j < nth; ++j)
+    for (int i = 0; i <= nr; ++i)
+      D[1][IDX(nrn, i, j)] -= gupper(g, g->rn[i], g->th[j], 7) *
+                              (phi[IDX(nrn, i, j + 1)] - phi[IDX(nrn, i, j)]) /
+                              dth;
+  for (int j = 1; j < nth; ++j)
+    for (int i = 1; i < nr; ++i) {
+      double dr = 0.5 * ((phi[IDX(nrn, i + 1, j)] - phi[IDX(nrn, i, j)]) /
+                             (g->rn[i + 1] - g->rn[i]) +
+                         (phi[IDX(nrn, i, j)] - phi[IDX(nrn, i - 1, j)]) /
+                             (g->rn[i] - g->rn[i - 1]));
+      D[2][IDX(nrn, i, j)] -= gupper(g, g->rn[i], g->tn[j], 9) * dr;
+    }
+  if (phi_out) memcpy(phi_out, phi, sizeof(double) * nn);
+  free(G);
+  free(phi);
+  free(nxt);
+}
+
+/* ------------------------------------------------------------------------
  * Maxwell solver (Sec. 2.1).  Grid fields
  *   E_i = alpha D_i + sqrt(g) eta_ijk beta^j B^k,
  *   H_i = alpha B_i - sqrt(g) eta_ijk beta^j D^k,
@@ -370,7 +531,6 @@ void om_deposit(const om_grid *g, double dt, long n, const double *r0,
  * single available neighbour is used.  E_phi vanishes on the theta edges
  * (axis condition, reading).
  * ------------------------------------------------------------------------ */
-#define IDX(nR, i, j) ((long)(j) * (nR) + (i))
 
 /* densitized average of a component at two positions (either may be -1) */
 static double davg2(const om_grid *g, int c, const double *F, int nR, int i0,
@@ -570,12 +730,14 @@ void om_ampere(const om_grid *g, double dt, const double *ab,
  *  3 E^{n+3/2} = E(D^{n+3/2}, B^{n+3/2})
  *  4 B^{n+2}   = B^{n+1} - dt curl E^{n+3/2}
  *  5 push x^{n+1} -> x^{n+2} in D^{n+3/2}, B^{n+3/2}
- *  6 deposit rho^{n+2}, J^{n+3/2}
+ *  6 deposit rho^{n+2}, J^{n+3/2} (conserving) or J^{n+2} (paper mode)
  *  7 H^{n+3/2} = H(B^{n+3/2}, D^{n+3/2})
- *  8 D^{n+2}   = D^{n+1} + dt (curl H^{n+3/2} - 4 pi J^{n+3/2})
+ *  8 D^{n+2}   = D^{n+1} + dt (curl H^{n+3/2} - 4 pi <J>^{n+3/2}),
+ *    <J>^{n+3/2} = J^{n+3/2}, or (J^{n+1} + J^{n+2}) / 2 in paper mode
  *  9 H^{n+2}   = H(B^{n+2}, D^{n+2})
  * 10 D^{n+5/2} = D^{n+3/2} + dt (curl H^{n+2} - 4 pi J^{n+2}),
- *    J^{n+2} = 1.5 J^{n+3/2} - 0.5 J^{n+1/2} (reading)
+ *    J^{n+2} = 1.5 J^{n+3/2} - 0.5 J^{n+1/2} (reading) or, in paper mode,
+ *    the deposited J^{n+2}
  * ------------------------------------------------------------------------ */
 static double *dup_zero(long n) { return (double *)calloc(n, sizeof(double)); }
 
@@ -644,8 +806,12 @@ void om_pic_step(const om_push_params *P, const om_grid *g, const double *ab,
       qw[k] = (p->qm[k] > 0 ? 1.0 : (p->qm[k] < 0 ? -1.0 : 0.0)) * p->w[k];
       mode[k] = was_alive[k] && (p->flags[k] & OM_ALIVE);
     }
-    om_deposit(g, dt, n, o[0], o[1], o[2], p->r, p->th, p->ph, qw, mode,
-               rho_new, J[0], J[1], J[2]);
+    if (P->deposit_mode == OM_DEPOSIT_PAPER)
+      om_deposit_paper(g, n, p->r, p->th, p->ur, p->uth, p->uph, qw, mode,
+                       rho_new, J[0], J[1], J[2]);
+    else
+      om_deposit(g, dt, n, o[0], o[1], o[2], p->r, p->th, p->ph, qw, mode,
+                 rho_new, J[0], J[1], J[2]);
     for (int c = 0; c < 6; ++c) free(G[c]);
     for (int c = 0; c < 3; ++c) free(o[c]);
     free(qw);
@@ -655,15 +821,20 @@ void om_pic_step(const om_push_params *P, const om_grid *g, const double *ab,
   /* 7 */
   om_compute_H(g, (const double *const *)F->Bh, (const double *const *)F->Dh1,
                H);
-  /* 8 */
+  /* 8: the conserving current is J^{n+3/2} itself; the paper's current is
+   * J^{n+2} at the new positions, averaged with J^{n+1}                   */
+  const int paper = P->deposit_mode == OM_DEPOSIT_PAPER;
+  for (int c = 0; c < 3; ++c)
+    for (long k = 0; k < sz[c]; ++k)
+      J2[c][k] = paper ? 0.5 * (J[c][k] + F->Jprev[c][k]) : J[c][k];
   om_ampere(g, dt, ab, (const double *const *)F->Dn, (const double *const *)H,
-            (const double *const *)J, Dnew);
+            (const double *const *)J2, Dnew);
   /* 9 */
   om_compute_H(g, (const double *const *)Bnew, (const double *const *)Dnew, H);
   /* 10 */
   for (int c = 0; c < 3; ++c)
     for (long k = 0; k < sz[c]; ++k)
-      J2[c][k] = 1.5 * J[c][k] - 0.5 * F->Jprev[c][k];
+      J2[c][k] = paper ? J[c][k] : 1.5 * J[c][k] - 0.5 * F->Jprev[c][k];
   om_ampere(g, dt, ab, (const double *const *)F->Dh1, (const double *const *)H,
             (const double *const *)J2, Dh2);
   /* rotate the time levels */

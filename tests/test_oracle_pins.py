@@ -612,6 +612,147 @@ def test_deposit_discrete_continuity_and_total_charge():
     assert abs(Q - qw.sum()) < 1e-12 * np.abs(qw).sum()
 
 
+def _paper_particles(g, n, seed):
+    rng = np.random.default_rng(seed)
+    z = np.c_[rng.uniform(g.rn[0], g.rn[-1], n), rng.uniform(g.th0, np.pi - g.th0, n),
+              rng.uniform(0, 6, n), rng.normal(0, 1, (n, 3))]
+    qw = rng.choice([-1.0, 1.0], n) * rng.uniform(0.5, 2, n)
+    return z, qw
+
+
+def test_paper_current_carries_each_particles_charge_flux():
+    """Sec. 2.3 (paper mode): summed over its subgrid with the dual volumes,
+    every component gives the total q w dx^i/dt with dx^i/dt of eq. p1 (the
+    weights are a partition of unity on every subgrid, positions off a half
+    subgrid included), and rho gives the total charge."""
+    a = 0.9
+    g = O.Grid(a, 16, 12, 1.3, 20.0)
+    z, qw = _paper_particles(g, 400, 11)
+    rho, Jr, Jt, Jp = O.deposit_paper(g, z, qw)
+    xdot = np.array([O.rhs(a, 0.0, zk)[:3] for zk in z])
+    Lr, Lt = _lengths(g)
+    dth = g.tn[1] - g.tn[0]
+    tp = 2 * np.pi
+    assert np.isclose((rho * tp * Lr[None, :] * Lt[:, None]).sum(), qw.sum(), rtol=1e-13)
+    assert np.isclose((Jr * tp * np.diff(g.rn)[None, :] * Lt[:, None]).sum(), qw @ xdot[:, 0],
+                      rtol=1e-12)
+    assert np.isclose((Jt * tp * Lr[None, :] * dth).sum(), qw @ xdot[:, 1], rtol=1e-12)
+    assert np.isclose((Jp * tp * Lr[None, :] * Lt[:, None]).sum(), qw @ xdot[:, 2], rtol=1e-12)
+
+
+def test_paper_current_of_a_particle_on_a_subgrid_point():
+    """A particle sitting on a J^r point (r_{i+1/2}, theta_j) gives all its
+    J^r to that point; on a J^theta point (r_i, theta_{j+1/2}) all its
+    J^theta; it moves with dx^i/dt = alpha gamma^ij u_j / Gamma - beta^i."""
+    a = 0.7
+    g = O.Grid(a, 10, 8, 1.8, 12.0)
+    i, j = 4, 3
+    u = np.array([0.3, -0.5, 1.1])
+    for pos, comp in (((g.rh[i], g.tn[j]), 0), ((g.rn[i], g.th[j]), 1)):
+        z = np.r_[pos, 0.0, u]
+        rho, Jr, Jt, Jp = O.deposit_paper(g, z[None], [1.0])
+        m = O.metric(a, pos[0], pos[1])
+        gi = np.array([[m[6], 0, m[9]], [0, m[7], 0], [m[9], 0, m[8]]])
+        Gam = np.sqrt(1 + u @ gi @ u)
+        v = m[0] * gi @ u / Gam - np.array([m[1], 0, 0])
+        J = (Jr, Jt)[comp]
+        k = np.unravel_index(np.abs(J).argmax(), J.shape)
+        assert k == (j, i)
+        Lr, Lt = _lengths(g)
+        vol = (2 * np.pi * (g.rn[i + 1] - g.rn[i]) * Lt[j] if comp == 0
+               else 2 * np.pi * Lr[i] * (g.tn[1] - g.tn[0]))
+        assert np.isclose(J[j, i] * vol, v[comp], rtol=1e-13)
+        others = np.delete(J.ravel(), np.ravel_multi_index((j, i), J.shape))
+        assert np.abs(others).max() <= 1e-15 * abs(J[j, i])
+
+
+def _stream_field(g, rng):
+    """D with zero discrete divergence at every interior node: the densitized
+    components are differences of one potential A on the cell centres."""
+    A = rng.normal(size=(g.nth + 2, g.nr + 2))  # centres, with a ghost ring
+    dth = g.tn[1] - g.tn[0]
+    Lr, _ = _lengths(g)
+    Dr = g.zeros(0)
+    Dt = g.zeros(1)
+    # sqrt(g) D^r at (i+1/2, j) = (A[j+1/2] - A[j-1/2]) / dth,
+    # sqrt(g) D^th at (i, j+1/2) = -(A[i+1/2] - A[i-1/2]) / Lr_i
+    Dr[:, :] = (A[1:, 1:-1] - A[:-1, 1:-1]) / dth
+    Dt[:, :] = -(A[1:-1, 1:] - A[1:-1, :-1]) / Lr[None, :]
+    return [g.densitize(0, Dr, -1), g.densitize(1, Dt, -1), g.zeros(6)]
+
+
+def test_cleaning_converged_removes_the_gauss_residual():
+    """Sec. 2.4, eq. phi: the cleaned D satisfies Gauss's law at every
+    interior node once the Jacobi iteration has converged (the residual is
+    measured by the independent om_gauss_residual); more sweeps, smaller
+    residual; B is not touched."""
+    a = 0.9
+    g = O.Grid(a, 10, 8, 1.3, 10.0)
+    D, B = O.wald_grid(g, 1.0)
+    z, qw = _paper_particles(g, 300, 12)
+    rho = O.deposit_paper(g, z, qw)[0]
+    G0 = np.abs(O.gauss_residual(g, D, rho)).max()
+    res = []
+    for iters in (50, 500, 5000):
+        Dc, phi = O.div_clean(g, D, rho, iters)
+        res.append(np.abs(O.gauss_residual(g, Dc, rho)).max())
+        assert np.all(phi[0] == 0) and np.all(phi[-1] == 0)
+        assert np.all(phi[:, 0] == 0) and np.all(phi[:, -1] == 0)
+    assert res[0] < G0 and res[1] < res[0] and res[2] < res[1]
+    assert res[2] < 1e-10 * G0
+
+
+def test_cleaning_keeps_a_field_that_obeys_gauss():
+    """A divergence-free D with rho = 0 (discrete Gauss holds at every
+    interior node) comes back unchanged up to round-off."""
+    a = 0.5
+    g = O.Grid(a, 12, 10, 1.9, 15.0)
+    D = _stream_field(g, np.random.default_rng(13))
+    rho = g.zeros(6)
+    assert np.abs(O.gauss_residual(g, D, rho)).max() < 1e-12 * max(np.abs(x).max() for x in D)
+    Dc, phi = O.div_clean(g, D, rho, 500)
+    assert np.abs(phi).max() < 1e-10
+    scale = max(np.abs(x).max() for x in D)
+    for c in range(3):
+        assert np.allclose(Dc[c], D[c], rtol=0, atol=1e-10 * scale)
+
+
+def test_paper_mode_step_breaks_gauss_and_cleaning_restores_it():
+    """Sec. 2.4: the paper's own current is not charge-conserving, so Gauss's
+    law drifts over paper-mode steps (the conserving deposit keeps it); the
+    paper's schedule (every 25 steps, 500 Jacobi sweeps) pulls it back."""
+    a = 0.9
+    g = O.Grid(a, 12, 10, 0.9 * _rplus(a), 12.0)
+    D, B = O.wald_grid(g, 1.0)
+    dt = 0.2 * min(np.diff(g.rn).min(), g.rn[0] * (g.tn[1] - g.tn[0]))
+    # shell far enough from both radial ends that no particle is removed (a
+    # removal takes its charge away without a current)
+    p0 = O.init_particles(O.INIT_SHELL_MJ, a, 5, 600, 4.0, 10.0, 0.2, 2.9, 0.3, w=0.05)
+    out = {}
+    for mode in (O.DEPOSIT_CONSERVING, O.DEPOSIT_PAPER):
+        F = O.Fields.uniform_levels(g, D, B)
+        p = p0.copy()
+        st = p.state()
+        alive = np.ones(p.n, np.int32)
+        F.rho[:] = O.deposit(g, dt, st[:, :3], st[:, :3], p.qm * p.w)[0]
+        if mode == O.DEPOSIT_PAPER:
+            rho, Jr, Jt, Jp = O.deposit_paper(g, st, p.qm * p.w, alive)
+            F.Jprev[0][:], F.Jprev[1][:], F.Jprev[2][:] = Jr, Jt, Jp
+        P = O.push_params(a, dt, field_kind=O.FIELDS_GRID, r_min=_rplus(a), r_max=12.0,
+                          th_lo=g.th0, th_hi=np.pi - g.th0, deposit_mode=mode)
+        G0 = np.abs(O.gauss_residual(g, F.Dn, F.rho)).max()
+        for _ in range(25):
+            O.pic_step(P, g, F, p)
+        assert np.all(p.flags & O.ALIVE)
+        out[mode] = (G0, np.abs(O.gauss_residual(g, F.Dn, F.rho)).max(), F)
+    G0, Gc, _ = out[O.DEPOSIT_CONSERVING]
+    assert abs(Gc - G0) < 1e-10 * max(G0, 1.0)
+    G0p, Gp, F = out[O.DEPOSIT_PAPER]
+    assert Gp > 100 * abs(Gc - G0) and Gp > 1e-6
+    Dc, _ = O.div_clean(g, F.Dn, F.rho, 500)
+    assert np.abs(O.gauss_residual(g, Dc, F.rho)).max() < 0.05 * Gp
+
+
 # ------------------------------------------------------------------ Maxwell
 def _rplus(a):
     return 1 + np.sqrt(1 - a * a)
