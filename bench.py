@@ -47,15 +47,24 @@ BYTES_DEPOSIT = 24 + 24 + 4 + 4 + 1 + 8 + 8 + 1
 # FP32 arrays read or written (two constitutive updates with their metric
 # coefficient tables and two curl updates)
 BYTES_FIELDS_PER_CELL = 65 * 4
+# the paper's current (deposit mode "paper"), per particle: r, theta, u_r,
+# u_theta, u_phi, w (FP64), q/m and flags, node weights W1..W3 and cell
+BYTES_DEPOSIT_PAPER = 6 * 8 + 1 + 1 + 24 + 4
+# divergence cleaning, per node and chain: every Jacobi sweep reads phi, the
+# source and the two face coefficients and writes phi (5 x 8 B); the source
+# and correction kernels about 100 B more
+BYTES_CLEAN_SWEEP = 40
+BYTES_CLEAN_FIXED = 100
 
 
 # Kernel per timing group, as named in rocprofv3 traces, and the source files
 # that determine its code: a committed counter summary is only used while its
 # recorded hash of these files still matches.
 GROUP_KERNEL = {"push": "k_push_explicit", "implicit": "k_push_implicit",
-                "deposit": "k_deposit", "fields": "k_ampere", "sort": "k_tile_scatter"}
+                "deposit": "k_deposit", "fields": "k_ampere", "sort": "k_tile_scatter",
+                "clean": "k_clean_jacobi"}
 GROUP_SOURCES = {"push": "push.hip", "implicit": "push.hip", "deposit": "deposit.hip",
-                 "fields": "maxwell.hip", "sort": "particles.hip"}
+                 "fields": "maxwell.hip", "sort": "particles.hip", "clean": "clean.hip"}
 
 
 def kernel_source_hash(group):
@@ -151,7 +160,9 @@ def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
         r_abs=W.get("r_abs", 0.0), chi0=1e4 if evolve else 0.0, lambda_abs=5.0,
         guess=G.GUESS_MLP if W.get("guess") == "mlp" else G.GUESS_RK4,
         sort_every=W.get("sort_every", 50),
-        push_waves_per_simd=push_wps)
+        push_waves_per_simd=push_wps,
+        deposit_mode=G.DEPOSIT_PAPER if W.get("deposit") == "paper" else G.DEPOSIT_CONSERVING,
+        clean_every=W.get("clean_every", 0), clean_iters=W.get("clean_iters", 500))
     if persistent_waves:
         cfg.persistent_waves = persistent_waves
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
@@ -384,6 +395,11 @@ def main():
                     help="steps between particle re-sorts (0: the workload's value)")
     ap.add_argument("--persistent-waves", type=int, default=0,
                     help="implicit-pass waves per CU (0: library default)")
+    ap.add_argument("--deposit", choices=("conserving", "paper"), default="conserving",
+                    help="deposit mode of the full-cycle workloads (paper: Sec. 2.3 current)")
+    ap.add_argument("--clean-every", type=int, default=0,
+                    help="divergence cleaning after every N-th step (Sec. 2.4; 0: never)")
+    ap.add_argument("--clean-iters", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -411,6 +427,15 @@ def main():
         W["n"] = args.particles
     if args.sort_every:
         W["sort_every"] = args.sort_every
+    if args.deposit != "conserving" or args.clean_every:
+        if W["mode"] != "evolve":
+            print("--deposit/--clean-every need a full-cycle workload (c3, c5)", file=sys.stderr)
+            sys.exit(2)
+        W["deposit"], W["clean_every"] = args.deposit, args.clean_every
+        W["clean_iters"] = args.clean_iters
+        W["desc"] += (f"; {args.deposit} deposit" +
+                      (f", cleaning every {args.clean_every} steps ({args.clean_iters} "
+                       "Jacobi sweeps)" if args.clean_every else ""))
     ctx, cfg = make_context(G, W, push_wps=args.push_wps,
                             persistent_waves=args.persistent_waves)
     print(f"[bench] workload {args.workload}: n={W['n']} dt={cfg.dt:.3e}", file=sys.stderr,
@@ -462,8 +487,14 @@ def main():
         "implicit": iters * flop_iter + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
     }
     roof = None
+    paper = W.get("deposit") == "paper"
+    bytes_dep = BYTES_DEPOSIT_PAPER if paper else BYTES_DEPOSIT
+    # counter summaries are taken on the default configuration of a workload
+    wl_key = args.workload + ("_paper" if paper else "") + \
+        ("_clean" if W.get("clean_every") else "")
     if not graph:
-        ms = {k: v[0] for k, v in tim.items()}
+        ms = {k: v[0] for k, v in tim.items()
+              if k in ("push", "implicit", "deposit", "fields") and v[1] > 0}
         dom = max(ms, key=ms.get)
         cnt = max(tim[dom][1], 1)
         avg_s = ms[dom] / cnt * 1e-3
@@ -472,19 +503,20 @@ def main():
             roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_FP64_TFLOPS,
-                    "traffic": counter_traffic(dom, args.workload, W["n"]),
+                    "traffic": counter_traffic(dom, wl_key, W["n"]),
                     "avg_launch_ms": avg_s * 1e3}
         else:
-            nbytes = BYTES_DEPOSIT * n_alive if dom == "deposit" else 0
+            nbytes = (bytes_dep * n_alive if dom == "deposit"
+                      else BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"])
             achieved = nbytes / avg_s / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                    "traffic": counter_traffic(dom, args.workload, W["n"]),
+                    "traffic": counter_traffic(dom, wl_key, W["n"]),
                     "avg_launch_ms": avg_s * 1e3}
         roof["algorithmic_bytes"] = BYTES_PUSH * n_alive if dom == "push" else None
         # every timing group against its own bound (per launch)
         groups = {}
-        for grp in ("push", "implicit", "deposit", "fields"):
+        for grp in ("push", "implicit", "deposit", "fields", "clean"):
             cnt_g = tim.get(grp, (0.0, 0))[1]
             if cnt_g == 0:
                 continue
@@ -494,13 +526,16 @@ def main():
                 groups[grp] = {"bound": "alu", "achieved": a_g, "peak": PEAK_FP64_TFLOPS,
                                "unit": "TFLOP/s", "frac": a_g / PEAK_FP64_TFLOPS}
             else:
-                nb = (BYTES_DEPOSIT * n_alive if grp == "deposit"
-                      else BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"])
+                nodes = (W["nr"] + 1) * (W["nth"] + 1)
+                nb = {"deposit": bytes_dep * n_alive,
+                      "fields": BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"],
+                      "clean": 2 * nodes * (BYTES_CLEAN_SWEEP * W.get("clean_iters", 500) +
+                                            BYTES_CLEAN_FIXED)}[grp]
                 a_g = nb / avg_g / 1e9
                 groups[grp] = {"bound": "hbm", "achieved": a_g, "peak": PEAK_HBM_GBS,
                                "unit": "GB/s", "frac": a_g / PEAK_HBM_GBS}
             groups[grp]["avg_launch_ms"] = avg_g * 1e3
-            groups[grp]["traffic"] = counter_traffic(grp, args.workload, W["n"])
+            groups[grp]["traffic"] = counter_traffic(grp, wl_key, W["n"])
         roof["groups"] = groups
         roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
                                       if v[1] > 0}

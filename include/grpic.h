@@ -72,6 +72,18 @@ enum grpic_field_mode {
   GRPIC_FIELDS_EVOLVE = 2  /* full PIC step: Maxwell + gather + push +
                               deposit                                      */
 };
+enum grpic_deposit_mode {
+  GRPIC_DEPOSIT_CONSERVING = 0, /* charge-conserving face fluxes over the
+                                   move (default); J^{n+3/2} in sub-step 8,
+                                   1.5 J^{n+3/2} - 0.5 J^{n+1/2} in 10      */
+  GRPIC_DEPOSIT_PAPER = 1       /* the paper's current (Sec. 2.3) at the
+                                   pushed state: each component on its own
+                                   Yee subgrid with that subgrid's volume
+                                   weights, carried by dx^i/dt (the grid
+                                   current alpha j - rho beta); sub-step 8
+                                   uses (J^{n+1} + J^{n+2}) / 2, 10 J^{n+2};
+                                   not charge-conserving: use cleaning     */
+};
 /* field time levels (Sec. 2.1 sub-steps; the push reads DH1 and BH) */
 enum grpic_level {
   GRPIC_LEVEL_DN = 0,  /* D^{n+1}                                          */
@@ -127,6 +139,11 @@ typedef struct grpic_config {
    * that reached t_end are no longer advanced (flags ALIVE, iters 0).     */
   double dt_implicit;    /* step of the implicit scheme (0: dt)            */
   double t_end;          /* end time of the particle clocks (0: none)      */
+  /* field_mode EVOLVE only: */
+  int deposit_mode;      /* enum grpic_deposit_mode                        */
+  int clean_every;       /* divergence cleaning after every N-th step (0:
+                            never; Sec. 2.4 uses 25)                       */
+  int clean_iters;       /* Jacobi sweeps per cleaning (Sec. 2.4: 500)     */
 } grpic_config;
 
 /* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */
@@ -293,6 +310,17 @@ int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
  * luminosity P(r_i) of eq. Pbz at every node radius (pbz may be NULL).    */
 int grpic_field_diagnostics(grpic_ctx *ctx, double *gauss_max,
                             double *divb_max, double *pbz);
+/* Divergence cleaning now (Sec. 2.4, eq. phi), as clean_every does after a
+ * step: on each D chain, iters Jacobi sweeps (FP64, from phi = 0, phi = 0 on
+ * the boundary nodes) of div(sqrt(g) g^kk d_k phi) = G with G the
+ * densitized Gauss residual at the interior nodes, then
+ * sqrt(g) D^i -= sqrt(g) g^ij d_j phi (D^r, D^theta on their faces, D^phi
+ * at interior nodes with the mean radial difference).  The integer chain
+ * (GRPIC_LEVEL_DN) is cleaned against rho of the last deposit, the half
+ * chain (GRPIC_LEVEL_DH1, half a step later) against 1.5 rho - 0.5 rho_prev.
+ * Allocates the solver's buffers on first use (five FP64 node arrays).
+ * GRPIC_E_STATE without field_mode EVOLVE; GRPIC_E_INVALID for iters < 1. */
+int grpic_clean(grpic_ctx *ctx, int iters);
 
 /* ---- timing ----------------------------------------------------------- */
 enum grpic_kernel_id {
@@ -302,7 +330,8 @@ enum grpic_kernel_id {
   GRPIC_K_DEPOSIT = 3,  /* deposit + finalize                              */
   GRPIC_K_SORT = 4,     /* tile sort                                       */
   GRPIC_K_GUESS = 5,    /* learned guess                                   */
-  GRPIC_K_COUNT = 6
+  GRPIC_K_CLEAN = 6,    /* divergence cleaning                             */
+  GRPIC_K_COUNT = 7
 };
 /* Enable (1) or disable (0) HIP-event timing of each kernel group on the
  * context's stream; grpic_get_timings returns the summed milliseconds and

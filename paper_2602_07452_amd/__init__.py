@@ -24,8 +24,9 @@ FIELDS_NONE, FIELDS_STATIC, FIELDS_EVOLVE = 0, 1, 2
 LEVEL_DN, LEVEL_DH0, LEVEL_DH1, LEVEL_BM, LEVEL_BN, LEVEL_BH, LEVEL_J, LEVEL_JPREV = range(8)
 INIT_ORBITS, INIT_SHELL_ISO, INIT_SHELL_MJ = 0, 1, 2
 FLAG_ALIVE, FLAG_IMPLICIT, FLAG_NOCONV, FLAG_REMOVED, FLAG_REFLECTED = 1, 2, 4, 8, 16
-K_FIELDS, K_PUSH, K_IMPLICIT, K_DEPOSIT, K_SORT, K_GUESS = range(6)
-KERNEL_NAMES = ("fields", "push", "implicit", "deposit", "sort", "guess")
+K_FIELDS, K_PUSH, K_IMPLICIT, K_DEPOSIT, K_SORT, K_GUESS, K_CLEAN = range(7)
+KERNEL_NAMES = ("fields", "push", "implicit", "deposit", "sort", "guess", "clean")
+DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
 HIST_BINS = 64
 MLP_NPARAM = 5510
 
@@ -46,7 +47,8 @@ class Config(C.Structure):
                 ("sort_every", C.c_int), ("tile_r", C.c_int), ("tile_th", C.c_int),
                 ("block", C.c_int), ("persistent_waves", C.c_int),
                 ("push_waves_per_simd", C.c_int), ("dt_implicit", C.c_double),
-                ("t_end", C.c_double)]
+                ("t_end", C.c_double), ("deposit_mode", C.c_int), ("clean_every", C.c_int),
+                ("clean_iters", C.c_int)]
 
 
 class InitSpec(C.Structure):
@@ -281,6 +283,10 @@ class Context:
                 "herr_hist": np.array(d.herr_hist[:]),
                 "deposit_fallback": d.deposit_fallback}
 
+    def clean(self, iters=500):
+        """Divergence cleaning of both D chains now (Sec. 2.4)."""
+        self._c("grpic_clean", C.c_int(iters))
+
     def field_diagnostics(self):
         g, b = C.c_double(), C.c_double()
         p = np.zeros(self.cfg.nr + 1)
@@ -295,10 +301,11 @@ class Context:
         self._c("grpic_reset_timings")
 
     def timings(self):
-        ms = np.zeros(6)
-        cnt = np.zeros(6, dtype=np.int64)
+        k = len(KERNEL_NAMES)  # GRPIC_K_COUNT
+        ms = np.zeros(k)
+        cnt = np.zeros(k, dtype=np.int64)
         self._c("grpic_get_timings", _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_long)))
-        return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(6)}
+        return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(k)}
 
     # -- learned guess
     def mlp_set(self, theta, mean, inv_std, scale):

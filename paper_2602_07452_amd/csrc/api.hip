@@ -94,6 +94,13 @@ void validate(const grpic_config& c) {
   if (!(c.dt_implicit >= 0.0 && std::isfinite(c.dt_implicit)))
     bad("dt_implicit must be finite and >= 0");
   if (!(c.t_end >= 0.0 && std::isfinite(c.t_end))) bad("t_end must be finite and >= 0");
+  if (c.deposit_mode != GRPIC_DEPOSIT_CONSERVING && c.deposit_mode != GRPIC_DEPOSIT_PAPER)
+    bad("unknown deposit_mode");
+  if (c.clean_every < 0) bad("clean_every must be >= 0");
+  if (c.clean_every > 0 && c.clean_iters < 1) bad("clean_iters must be >= 1");
+  if ((c.deposit_mode != GRPIC_DEPOSIT_CONSERVING || c.clean_every > 0) &&
+      c.field_mode != GRPIC_FIELDS_EVOLVE)
+    bad("deposit_mode and clean_every need field_mode EVOLVE");
   if ((c.dt_implicit > 0.0 && c.dt_implicit != c.dt) || c.t_end > 0.0) {
     if (c.field_mode != GRPIC_FIELDS_NONE)
       bad("steps of their own length and t_end need field_mode NONE");
@@ -309,6 +316,9 @@ void free_all(grpic_ctx* c) {
   }
   for (int s = 0; s < 2; ++s)
     for (int q = 0; q < 4; ++q) dfree(c->J[s][q]);
+  for (double* p : {c->clean_kr, c->clean_kt, c->clean_kp, c->clean_src, c->clean_phi[0],
+                    c->clean_phi[1]})
+    dfree(p);
   dfree(c->acc.Q);
   dfree(c->acc.P);
   dfree(c->acc.Fr);
@@ -400,6 +410,8 @@ void run_step(grpic_ctx* c) {
     GRPIC_HIP(hipGraphLaunch(c->graph_exec[key], c->stream));
     advance_host_state(c);
   }
+  if (c->cfg.clean_every > 0 && c->steps % c->cfg.clean_every == 0)
+    launch_clean(c, c->cfg.clean_iters);  // eager, after the step
   if (c->cfg.sort_every > 0 && c->cfg.field_mode != GRPIC_FIELDS_NONE &&
       c->steps % c->cfg.sort_every == 0)
     launch_sort(c);  // swaps the buffer sets: the other cached graphs apply
@@ -537,6 +549,9 @@ int grpic_config_default(grpic_config* cfg) {
   cfg->tile_th = 16;
   cfg->block = 256;
   cfg->persistent_waves = 8;
+  cfg->deposit_mode = GRPIC_DEPOSIT_CONSERVING;
+  cfg->clean_every = 0;
+  cfg->clean_iters = 500;
   return GRPIC_OK;
 }
 
@@ -948,6 +963,17 @@ int grpic_field_diagnostics(grpic_ctx* c, double* gauss_max, double* divb_max,
     check_ctx(c);
     if (c->nr == 0) throw Error(GRPIC_E_STATE, "context has no grid");
     launch_field_diag(c, gauss_max, divb_max, pbz);
+  });
+}
+
+int grpic_clean(grpic_ctx* c, int iters) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (c->cfg.field_mode != GRPIC_FIELDS_EVOLVE)
+      throw Error(GRPIC_E_STATE, "cleaning needs field_mode EVOLVE");
+    if (iters < 1) throw Error(GRPIC_E_INVALID, "iters must be >= 1");
+    launch_clean(c, iters);
+    GRPIC_HIP(hipStreamSynchronize(c->stream));
   });
 }
 

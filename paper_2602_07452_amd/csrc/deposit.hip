@@ -393,6 +393,104 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
   }
 }
 
+// ---------------------------------------------------- the paper's current
+// Sec. 2.3 as a deposit mode of its own: every particle alive after the push
+// deposits at its state (x, u): rho and J^phi with the node weights (W1..W3
+// and the node cell given), J^r on (r_{i+1/2}, th_j) and J^theta on
+// (r_i, th_{j+1/2}) with the volume weights of that subgrid's cell, each
+// carried by the coordinate velocity dx^i/dt = alpha g^ij u_j / Gamma -
+// beta^i (the grid current alpha j - rho beta of eq. m3).  A position off a
+// half subgrid is moved onto its edge for that component.  The integers
+// accumulated are the finalize kernel's units: charge for rho, charge times
+// dt (and over the subgrid spacing for J^r, J^theta) for the currents.
+__global__ __launch_bounds__(256) void k_deposit_paper(DepArgs A, const double* W1,
+                                                       const double* W2, const double* W3,
+                                                       const int* cell, double dt) {
+  const ParticleView& P = A.p;
+  const GridView& g = A.g;
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) return;
+  const double qw = (double)P.qm[k] * P.w[k], s = A.acc.scale;
+  const double r = P.r[k], th = P.th[k];
+  const double ur = P.ur[k], ut = P.uth[k], up = P.uph[k];
+  Met m;
+  metric(g.a, r, th, m);
+  const double Gam = sqrt(1.0 + m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
+                          2.0 * m.irp * ur * up);
+  const double aG = m.alpha / Gam;
+  const double vr = aG * (m.irr * ur + m.irp * up) - m.betar;
+  const double vt = aG * m.itt * ut;
+  const double vp = aG * (m.irp * ur + m.ipp * up);
+  int p, q;
+  split_cell(A, cell[k], p, q);
+  const int nrn = A.nr + 1;
+  auto add = [&](long long* acc, long idx, double v) {
+    long long iv = llrint(v * s);
+    if (iv != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(acc + idx),
+                static_cast<unsigned long long>(iv));
+  };
+  // rho and J^phi on the nodes
+  {
+    const double w1 = W1[k], w2 = W2[k], w3 = W3[k];
+    const double W[4] = {1.0 - w1 - w2 - w3, w1, w2, w3};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      long nn = (long)(q + (c >> 1)) * nrn + p + (c & 1);
+      add(A.acc.Q, nn, qw * W[c]);
+      add(A.acc.P, nn, qw * W[c] * vp * dt);
+    }
+  }
+  double st, ct;
+  fsincos(th, &st, &ct);
+  // J^r on (r_{i+1/2}, th_j): the half-radius cell of r, row q
+  {
+    const double rc = fmin(fmax(r, g.rh[0]), g.rh[A.nr - 1]);
+    int pr = rc >= g.rh[p] ? p : p - 1;
+    pr = pr < 0 ? 0 : (pr > A.nr - 2 ? A.nr - 2 : pr);
+    double W[4];
+    dep_weights_box(g, rc, th, st, ct, g.rh[pr], g.rh[pr + 1], theta_node(g, q),
+                    theta_node(g, q + 1), g.stn[q], g.ctn[q], W);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int i = pr + (c & 1), j = q + (c >> 1);
+      add(A.acc.Fr, (long)j * A.nr + i, qw * W[c] * vr * dt * g.idrn[i]);
+    }
+  }
+  // J^theta on (r_i, th_{j+1/2}): the half-angle cell of th, column p
+  {
+    const double tc = fmin(fmax(th, g.th[0]), g.th[A.nth - 1]);
+    int qt = tc >= g.th[q] ? q : q - 1;
+    qt = qt < 0 ? 0 : (qt > A.nth - 2 ? A.nth - 2 : qt);
+    double sc, cc, sa, ca;
+    fsincos(tc, &sc, &cc);
+    fsincos(g.th[qt], &sa, &ca);
+    double W[4];
+    dep_weights_box(g, r, tc, sc, cc, g.rn[p], g.rn[p + 1], g.th[qt], g.th[qt + 1], sa, ca,
+                    W);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int i = p + (c & 1), j = qt + (c >> 1);
+      add(A.acc.Ft, (long)j * nrn + i, qw * W[c] * vt * dt * g.inv_dth);
+    }
+  }
+}
+
+static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int* cell) {
+  DepArgs A;
+  A.g = make_grid_view(c);
+  A.p = c->pv;
+  A.p.n = c->n;
+  A.acc = c->acc;
+  A.nr = c->nr;
+  A.nth = c->nth;
+  A.inv_nr = 1.0 / c->nr;
+  hipLaunchKernelGGL(k_deposit_paper, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream,
+                     A, W[1], W[2], W[3], cell, c->cfg.dt);
+  GRPIC_HIP(hipGetLastError());
+}
+
 // weights and node cell of the current positions
 __global__ __launch_bounds__(256) void k_weights(GridView g, ParticleView P) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,7 +556,10 @@ static void finalize(grpic_ctx* c, int which) {
 void launch_deposit(grpic_ctx* c) {
   hipEvent_t ev;
   time_begin(c, GRPIC_K_DEPOSIT, &ev);
-  if (c->n > 0) {
+  if (c->n > 0 && c->cfg.deposit_mode == GRPIC_DEPOSIT_PAPER) {
+    // J^{n+2} at the pushed state (new weights and cells)
+    launch_deposit_paper(c, c->pv.Wn, c->pv.celln);
+  } else if (c->n > 0) {
     DepArgs A;
     A.g = grid_view(c);
     A.p = c->pv;
@@ -495,11 +596,15 @@ void launch_deposit_initial(grpic_ctx* c) {
     A.nr = c->nr;
     A.nth = c->nth;
     A.inv_nr = 1.0 / c->nr;
-    hipLaunchKernelGGL(k_deposit_rho, dim3(grid_for(c->n, 256)), dim3(256), 0,
-                       c->stream, A);
+    if (c->cfg.deposit_mode == GRPIC_DEPOSIT_PAPER)
+      launch_deposit_paper(c, P.W, P.cell);  // rho and J at the loaded state
+    else
+      hipLaunchKernelGGL(k_deposit_rho, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                         c->stream, A);
     GRPIC_HIP(hipGetLastError());
   }
-  finalize(c, c->jcur);  // initial rho (and zero currents) in J[jcur]
+  // initial rho (conserving: zero currents; paper: J^{n+1}) in J[jcur]
+  finalize(c, c->jcur);
 }
 
 }  // namespace grpic

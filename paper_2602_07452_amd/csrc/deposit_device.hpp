@@ -37,15 +37,13 @@ __device__ __forceinline__ void sincos_steps(double s0, double c0, double h,
   }
 }
 
-// W[0..3] for nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1); st, ct = sin, cos
-// of th
-// ra, rb: radii of the cell's node columns; sq, cq: sin, cos of its lower
-// node angle
-__device__ __forceinline__ void dep_weights_at(const GridView& g, double r, double th,
-                                               double st, double ct, double ra, double rb,
-                                               double sq, double cq, int q, double* W) {
+// W[0..3] for the corners (ra,ta), (rb,ta), (ra,tb), (rb,tb) of any cell;
+// st, ct = sin, cos of th; sq, cq: sin, cos of ta
+__device__ __forceinline__ void dep_weights_box(const GridView& g, double r, double th,
+                                                double st, double ct, double ra, double rb,
+                                                double ta, double tb, double sq, double cq,
+                                                double* W) {
   const double a2 = g.a * g.a;
-  double ta = theta_node(g, q), tb = theta_node(g, q + 1);
   double h1r = (r - ra) * (1.0 / 3.0), h2r = (rb - r) * (1.0 / 3.0);
   double h1t = (th - ta) * (1.0 / 3.0), h2t = (tb - th) * (1.0 / 3.0);
   // 7 radii ra + i h1r (i = 0..2), r, r + i h2r (i = 1..3), and 7 angles the
@@ -103,6 +101,16 @@ __device__ __forceinline__ void dep_weights_at(const GridView& g, double r, doub
   W[1] = Vab * iV;
   W[2] = Vba * iV;
   W[3] = Vaa * iV;
+}
+
+// W[0..3] for nodes (p,q), (p+1,q), (p,q+1), (p+1,q+1) of node cell row q;
+// ra, rb: radii of the cell's node columns; sq, cq: sin, cos of its lower
+// node angle
+__device__ __forceinline__ void dep_weights_at(const GridView& g, double r, double th,
+                                               double st, double ct, double ra, double rb,
+                                               double sq, double cq, int q, double* W) {
+  dep_weights_box(g, r, th, st, ct, ra, rb, theta_node(g, q), theta_node(g, q + 1), sq, cq,
+                  W);
 }
 
 __device__ __forceinline__ void dep_weights(const GridView& g, double r,

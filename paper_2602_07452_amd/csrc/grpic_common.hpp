@@ -124,6 +124,11 @@ struct grpic_ctx {
   int ntiles = 0;
   double qw_max = 0;
   long steps = 0;
+  // divergence cleaning (allocated on first use): coefficients
+  // sqrt(g) g^rr / dr on the D^r faces, sqrt(g) g^thth / dth on the D^theta
+  // faces, sqrt(g) g^phir on the nodes; the Gauss residual; phi ping-pong
+  double *clean_kr = nullptr, *clean_kt = nullptr, *clean_kp = nullptr;
+  double *clean_src = nullptr, *clean_phi[2]{};
   // learned guess
   bool mlp_ready = false;
   void* mlp = nullptr;
@@ -176,6 +181,7 @@ void launch_deposit_initial(grpic_ctx* c);
 void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,
                            const double* mj_table, int mj_k, double mj_h);
 void launch_energy_H0(grpic_ctx* c);
+void launch_clean(grpic_ctx* c, int iters);  // Sec. 2.4, both D chains
 void launch_sort(grpic_ctx* c);
 void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,

@@ -421,13 +421,18 @@ void launch_fields_step_post(grpic_ctx* c) {
   dim3 g(grid_for(n, 256)), b(256);
   dim3 gb(grid_for(c->nth + 1, 256));
   Level4 Jc = jlevel(c, c->jcur ^ 1), Jp = jlevel(c, c->jcur);
+  // conserving deposit: J^{n+3/2}, then 1.5 J^{n+3/2} - 0.5 J^{n+1/2};
+  // the paper's current: (J^{n+1} + J^{n+2}) / 2, then J^{n+2}
+  const bool paper = c->cfg.deposit_mode == GRPIC_DEPOSIT_PAPER;
+  const float c8 = paper ? 0.5f : 1.0f, p8 = paper ? 0.5f : 0.0f;
+  const float c10 = paper ? 1.0f : 1.5f, p10 = paper ? 0.0f : -0.5f;
   hipLaunchKernelGGL(k_compute_H, g, b, 0, c->stream, F, c->B[2], c->D[2], c->H);
   hipLaunchKernelGGL(k_ampere, g, b, 0, c->stream, F, c->D[0], c->H, Jc, Jp,
-                     1.0f, 0.0f, c->D[0]);
+                     c8, p8, c->D[0]);
   hipLaunchKernelGGL(k_radial_bc, gb, b, 0, c->stream, F, c->D[0]);
   hipLaunchKernelGGL(k_compute_H, g, b, 0, c->stream, F, c->B[0], c->D[0], c->H);
   hipLaunchKernelGGL(k_ampere, g, b, 0, c->stream, F, c->D[2], c->H, Jc, Jp,
-                     1.5f, -0.5f, c->D[1]);
+                     c10, p10, c->D[1]);
   hipLaunchKernelGGL(k_radial_bc, gb, b, 0, c->stream, F, c->D[1]);
   GRPIC_HIP(hipGetLastError());
 }

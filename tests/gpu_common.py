@@ -97,3 +97,33 @@ def compare_push(cfg, before, after, P, grid=None, G6=None, tol=TOL_STATE, t=Non
     herr_ok = np.abs(after["herr"][alive] - p.herr[alive]) <= 1e-11 + 1e-6 * np.abs(p.herr[alive])
     assert herr_ok.all(), np.abs(after["herr"][alive] - p.herr[alive]).max()
     return float(err.max()), p
+
+
+def levels(ctx):
+    """Every field level of the context (host copies)."""
+    return {lev: [ctx.get_field(lev, c) for c in range(4 if lev >= G.LEVEL_J else 3)]
+            for lev in range(8)}
+
+
+def oracle_fields(g, S):
+    """Oracle fields (plain values) from the GPU levels S."""
+    F = O.Fields(g)
+    dd = lambda lev, off: [g.densitize(off + c, S[lev][c].astype(np.float64), -1)
+                           for c in range(3)]
+    F.Dn, F.Dh0, F.Dh1 = dd(G.LEVEL_DN, 0), dd(G.LEVEL_DH0, 0), dd(G.LEVEL_DH1, 0)
+    F.Bm, F.Bn, F.Bh = dd(G.LEVEL_BM, 3), dd(G.LEVEL_BN, 3), dd(G.LEVEL_BH, 3)
+    F.Jprev = [S[G.LEVEL_J][c].astype(np.float64) for c in range(3)]
+    F.rho = S[G.LEVEL_J][3].astype(np.float64)
+    return F
+
+
+def field_errors(g, F, S1):
+    """Components of the GPU levels S1 off the oracle fields F by more than
+    TOL_FIELD (relative max norm)."""
+    errs = {}
+    for name, lev, arrs, off in (("Dn", G.LEVEL_DN, F.Dn, 0), ("Dh0", G.LEVEL_DH0, F.Dh0, 0),
+                                 ("Dh1", G.LEVEL_DH1, F.Dh1, 0), ("Bm", G.LEVEL_BM, F.Bm, 3),
+                                 ("Bn", G.LEVEL_BN, F.Bn, 3), ("Bh", G.LEVEL_BH, F.Bh, 3)):
+        for c in range(3):
+            errs[f"{name}{c}"] = norm_err(S1[lev][c], g.densitize(off + c, arrs[c]))
+    return {k: v for k, v in errs.items() if not v <= TOL_FIELD}

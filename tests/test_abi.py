@@ -57,3 +57,20 @@ def test_invalid_config_is_rejected_without_gpu():
     cfg = G.config_default(a=1.5)
     with pytest.raises(G.GrpicError):
         G.Context(cfg)
+
+
+def test_paper_deposit_and_cleaning_need_evolving_fields():
+    for kw in (dict(deposit_mode=G.DEPOSIT_PAPER), dict(clean_every=25),
+               dict(deposit_mode=7, field_mode=G.FIELDS_EVOLVE)):
+        base = dict(a=0.9, nr=16, nth=16, r_in=1.3, r_out=10.0, field_mode=G.FIELDS_STATIC)
+        base.update(kw)
+        with pytest.raises(G.GrpicError):
+            G.Context(G.config_default(**base))
+
+
+def test_kernel_group_names_match_the_header():
+    """The binding sizes the timing buffers by its list of group names."""
+    import re
+    text = open(G.HEADER).read()
+    count = int(re.search(r"GRPIC_K_COUNT\s*=\s*(\d+)", text).group(1))
+    assert count == len(G.KERNEL_NAMES)

@@ -7,8 +7,11 @@ import pytest
 
 import oracle as O
 import paper_2602_07452_amd as G
-from gpu_common import (TOL_FIELD, TOL_STATE, compare_push, gpu_fields_as_G, norm_err,
-                        oracle_grid, oracle_particles, push_params_from, rplus)
+from gpu_common import (TOL_STATE, compare_push, gpu_fields_as_G, norm_err, oracle_grid,
+                        oracle_particles, push_params_from, rplus)
+from gpu_common import field_errors as _field_errors
+from gpu_common import levels as _levels
+from gpu_common import oracle_fields as _oracle_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -23,32 +26,6 @@ def _pic_cfg(a=0.99, n=2048, nr=40, nth=32):
                            lambda_abs=5.0, tile_r=16, tile_th=16)
     cfg.dt = 0.5 * G.cfl_dt(cfg)
     return cfg
-
-
-def _levels(ctx):
-    return {lev: [ctx.get_field(lev, c) for c in range(4 if lev >= G.LEVEL_J else 3)]
-            for lev in range(8)}
-
-
-def _oracle_fields(g, S):
-    F = O.Fields(g)
-    dd = lambda lev, off: [g.densitize(off + c, S[lev][c].astype(np.float64), -1)
-                           for c in range(3)]
-    F.Dn, F.Dh0, F.Dh1 = dd(G.LEVEL_DN, 0), dd(G.LEVEL_DH0, 0), dd(G.LEVEL_DH1, 0)
-    F.Bm, F.Bn, F.Bh = dd(G.LEVEL_BM, 3), dd(G.LEVEL_BN, 3), dd(G.LEVEL_BH, 3)
-    F.Jprev = [S[G.LEVEL_J][c].astype(np.float64) for c in range(3)]
-    F.rho = S[G.LEVEL_J][3].astype(np.float64)
-    return F
-
-
-def _field_errors(g, F, S1):
-    errs = {}
-    for name, lev, arrs, off in (("Dn", G.LEVEL_DN, F.Dn, 0), ("Dh0", G.LEVEL_DH0, F.Dh0, 0),
-                                 ("Dh1", G.LEVEL_DH1, F.Dh1, 0), ("Bm", G.LEVEL_BM, F.Bm, 3),
-                                 ("Bn", G.LEVEL_BN, F.Bn, 3), ("Bh", G.LEVEL_BH, F.Bh, 3)):
-        for c in range(3):
-            errs[f"{name}{c}"] = norm_err(S1[lev][c], g.densitize(off + c, arrs[c]))
-    return {k: v for k, v in errs.items() if not v <= TOL_FIELD}
 
 
 def _grid_point_particles(ctx, cfg):
