@@ -403,14 +403,12 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
 // half subgrid is moved onto its edge for that component.  The integers
 // accumulated are the finalize kernel's units: charge for rho, charge times
 // dt (and over the subgrid spacing for J^r, J^theta) for the currents.
-__global__ __launch_bounds__(256) void k_deposit_paper(DepArgs A, const double* W1,
-                                                       const double* W2, const double* W3,
-                                                       const int* cell, double dt) {
+template <class Sink>
+__device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const double* W1,
+                               const double* W2, const double* W3, const int* cell,
+                               double dt) {
   const ParticleView& P = A.p;
   const GridView& g = A.g;
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= P.n) return;
-  if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) return;
   const double qw = (double)P.qm[k] * P.w[k], s = A.acc.scale;
   const double r = P.r[k], th = P.th[k];
   const double ur = P.ur[k], ut = P.uth[k], up = P.uph[k];
@@ -424,22 +422,15 @@ __global__ __launch_bounds__(256) void k_deposit_paper(DepArgs A, const double* 
   const double vp = aG * (m.irp * ur + m.ipp * up);
   int p, q;
   split_cell(A, cell[k], p, q);
-  const int nrn = A.nr + 1;
-  auto add = [&](long long* acc, long idx, double v) {
-    long long iv = llrint(v * s);
-    if (iv != 0)
-      atomicAdd(reinterpret_cast<unsigned long long*>(acc + idx),
-                static_cast<unsigned long long>(iv));
-  };
   // rho and J^phi on the nodes
   {
     const double w1 = W1[k], w2 = W2[k], w3 = W3[k];
     const double W[4] = {1.0 - w1 - w2 - w3, w1, w2, w3};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      long nn = (long)(q + (c >> 1)) * nrn + p + (c & 1);
-      add(A.acc.Q, nn, qw * W[c]);
-      add(A.acc.P, nn, qw * W[c] * vp * dt);
+      const int i = p + (c & 1), j = q + (c >> 1);
+      sink_add(S, 0, i, j, qw * W[c], s);
+      sink_add(S, 1, i, j, qw * W[c] * vp * dt, s);
     }
   }
   double st, ct;
@@ -454,8 +445,8 @@ __global__ __launch_bounds__(256) void k_deposit_paper(DepArgs A, const double* 
                     theta_node(g, q + 1), g.stn[q], g.ctn[q], W);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      int i = pr + (c & 1), j = q + (c >> 1);
-      add(A.acc.Fr, (long)j * A.nr + i, qw * W[c] * vr * dt * g.idrn[i]);
+      const int i = pr + (c & 1), j = q + (c >> 1);
+      sink_add(S, 2, i, j, qw * W[c] * vr * dt * g.idrn[i], s);
     }
   }
   // J^theta on (r_i, th_{j+1/2}): the half-angle cell of th, column p
@@ -471,9 +462,75 @@ __global__ __launch_bounds__(256) void k_deposit_paper(DepArgs A, const double* 
                     W);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      int i = p + (c & 1), j = qt + (c >> 1);
-      add(A.acc.Ft, (long)j * nrn + i, qw * W[c] * vt * dt * g.inv_dth);
+      const int i = p + (c & 1), j = qt + (c >> 1);
+      sink_add(S, 3, i, j, qw * W[c] * vt * dt * g.inv_dth, s);
     }
+  }
+}
+
+// one block per chunk of kDepChunk sorted particles: the chunk's node box
+// (widened one node down, where the half-subgrid cells start) is summed in
+// LDS and flushed with one global atomic per touched entry; a chunk whose
+// box does not fit goes to global atomics directly
+__global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const double* W1,
+                                                             const double* W2,
+                                                             const double* W3,
+                                                             const int* cell, double dt) {
+  __shared__ long long bins[4 * kDepBins];
+  __shared__ int box[4];
+  const ParticleView& P = A.p;
+  const long beg = (long)blockIdx.x * kDepChunk;
+  const long end = min(beg + (long)kDepChunk, P.n);
+  if (threadIdx.x == 0) {
+    box[0] = 1 << 30;
+    box[1] = -1;
+    box[2] = 1 << 30;
+    box[3] = -1;
+  }
+  __syncthreads();
+  int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
+  for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
+    if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) continue;
+    int p, q;
+    split_cell(A, cell[k], p, q);
+    pmin = min(pmin, p);
+    pmax = max(pmax, p);
+    qmin = min(qmin, q);
+    qmax = max(qmax, q);
+  }
+  if (pmax >= 0) {
+    atomicMin(&box[0], pmin);
+    atomicMax(&box[1], pmax);
+    atomicMin(&box[2], qmin);
+    atomicMax(&box[3], qmax);
+  }
+  __syncthreads();
+  if (box[1] < 0) return;  // nothing charged in this chunk
+  const int bp0 = max(box[0] - 1, 0), bq0 = max(box[2] - 1, 0);
+  const int bw = box[1] + 2 - bp0, bh = box[3] + 2 - bq0;
+  if (bw * bh > kDepBins) {
+    if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
+    GlobalSink Gs{&A.acc, A.nr};
+    for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
+      if ((P.flags[k] & GRPIC_FLAG_ALIVE) && P.qm[k] != 0)
+        paper_particle(A, Gs, k, W1, W2, W3, cell, dt);
+    return;
+  }
+  LdsSink L{bins, bp0, bq0, bw, bw * bh};
+  for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
+  __syncthreads();
+  for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
+    if ((P.flags[k] & GRPIC_FLAG_ALIVE) && P.qm[k] != 0)
+      paper_particle(A, L, k, W1, W2, W3, cell, dt);
+  __syncthreads();
+  GlobalSink Gs{&A.acc, A.nr};
+  for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
+    long long v = bins[i];
+    if (v == 0) continue;
+    int a = i / L.n, rr = i - a * L.n;
+    int jj = rr / bw, ii = rr - jj * bw;
+    atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
+              static_cast<unsigned long long>(v));
   }
 }
 
@@ -486,8 +543,9 @@ static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int
   A.nr = c->nr;
   A.nth = c->nth;
   A.inv_nr = 1.0 / c->nr;
-  hipLaunchKernelGGL(k_deposit_paper, dim3(grid_for(c->n, 256)), dim3(256), 0, c->stream,
-                     A, W[1], W[2], W[3], cell, c->cfg.dt);
+  A.fallback = &c->stats->deposit_fallback;
+  hipLaunchKernelGGL(k_deposit_paper, dim3(grid_for(c->n, kDepChunk)), dim3(kDepBlock), 0,
+                     c->stream, A, W[1], W[2], W[3], cell, c->cfg.dt);
   GRPIC_HIP(hipGetLastError());
 }
 
