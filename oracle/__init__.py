@@ -78,6 +78,7 @@ def lib():
         L.om_mlp_loss_grad.restype = C.c_double
         L.om_step_imr.restype = C.c_int
         L.om_step_ham.restype = C.c_int
+        L.om_inject.restype = C.c_long
         _LIB = L
     return _LIB
 
@@ -451,6 +452,32 @@ def wald_grid(grid, B0, a_field=None):
     af = grid.a if a_field is None else a_field
     lib().om_wald_grid(grid.h, C.c_double(B0), C.c_double(af), _ptrs(D), _ptrs(B))
     return D, B
+
+
+class InjectParams(C.Structure):
+    _fields_ = [("r0", C.c_double), ("r1", C.c_double), ("mult", C.c_double),
+                ("density", C.c_double), ("theta", C.c_double), ("seed", C.c_uint64)]
+
+
+def inject(grid, params, event, B, particles, room):
+    """Pair injection (Sec. 3.3) into `particles` (appended, returns a new
+    Particles) from the plain B^r, B^theta; at most `room` new particles."""
+    p = particles
+    out = np.zeros((max(room, 0), 8))
+    flags = np.ascontiguousarray(p.flags, np.int32)
+    made = lib().om_inject(grid.h, C.byref(params), C.c_uint64(event), _p(_f64(B[0])),
+                           _p(_f64(B[1])), C.c_long(p.n), _p(p.r), _p(p.th), _p(p.qm),
+                           _p(p.w), _ip(flags), C.c_long(room), _p(out))
+    new = out[:made]
+    q = Particles(p.n + made)
+    for k in Particles.KEYS:
+        getattr(q, k)[:p.n] = getattr(p, k)
+    q.flags[:p.n], q.iters[:p.n] = p.flags, p.iters
+    for i, k in enumerate(("r", "th", "ph", "ur", "uth", "uph", "qm", "w")):
+        getattr(q, k)[p.n:] = new[:, i]
+    q.H0[p.n:] = [energy(grid.a, z) for z in new[:, :6]]
+    q.crit[p.n:] = np.nan
+    return q
 
 
 def split_monopole_grid(grid, B0, zeta0):

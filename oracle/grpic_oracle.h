@@ -205,6 +205,19 @@ void om_div_B(const om_grid *g, const double *const *B, double *out);
 void om_poynting(const om_grid *g, const double *const *D,
                  const double *const *B, double *out);
 
+/* ---- pair injection (Sec. 3.3) -------------------------------------------*/
+typedef struct {
+  double r0, r1;   /* cells whose centre radius lies in [r0, r1]            */
+  double mult;     /* inject while n < mult * n_GJ                          */
+  double density;  /* an injected pair adds density * n_GJ                  */
+  double theta;    /* Maxwell-Juettner temperature of the injected momenta  */
+  uint64_t seed;
+} om_inject_params;
+long om_inject(const om_grid *g, const om_inject_params *I, uint64_t event,
+               const double *Br, const double *Bt, long n, const double *r,
+               const double *th, const double *qm, const double *w,
+               const int *flags, long room, double *out);
+
 /* ---- initial data (App. B, Sec. 3.3) -------------------------------------*/
 void om_wald_grid(const om_grid *g, double B0, double af, double *const *D,
                   double *const *B);

@@ -104,6 +104,8 @@ static int locate(const double *x, int n, double v) {
   return lo;
 }
 
+int om_locate(const double *x, int n, double v) { return locate(x, n, v); }
+
 static double clamp01(double f) { return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f); }
 
 /* ------------------------------------------------------------------------

@@ -162,3 +162,78 @@ void om_init_particles(int kind, double a, uint64_t seed, long n, double r0,
   }
   free(T);
 }
+
+/* ------------------------------------------------------------------------
+ * Pair injection (Sec. 3.3).  Every node cell (p, q) whose centre
+ * (r_{p+1/2}, theta_{q+1/2}) lies in [r0, r1] receives one e+/e- pair at one
+ * position when its plasma density n = sum of the weights of the charged
+ * particles in the cell / V_cell is below mult * n_GJ.  Readings:
+ *   n_GJ = Omega_H |Omega . B| / (4 pi) per unit Omega_H, with the rotation
+ *          axis direction taken as the gradient of z = r cos(theta):
+ *          Omega . B = Omega_H (cos(theta) B^r - r sin(theta) B^theta),
+ *          Omega_H = a / (2 r_+), B at the cell centre as the mean of the
+ *          densitized values on the two faces over sqrt(g) at the centre;
+ *   V_cell = 2 pi sqrt(g)(centre) (r_{p+1} - r_p) dtheta;
+ *   each particle of the pair weighs density * n_GJ * V_cell / 2, so the
+ *          pair adds density * n_GJ;
+ *   cells are visited in index order q n_r + p while there is room for a
+ *          pair; the pair's position is uniform in proper volume over the
+ *          cell (stream c = q n_r + p), the momenta Maxwell-Juettner at
+ *          temperature theta in the FIDO frame (streams 2c and 2c + 1), all
+ *          from the seed seed + event * golden gamma.
+ * B: plain B^r (at (r_i, theta_{j+1/2})) and B^theta (at (r_{i+1/2},
+ * theta_j)).  Writes 8 values per new particle (r, theta, phi, u_r, u_theta,
+ * u_phi, q/m, w) and returns the number written.
+ * ------------------------------------------------------------------------ */
+long om_inject(const om_grid *g, const om_inject_params *I, uint64_t event,
+               const double *Br, const double *Bt, long n, const double *r,
+               const double *th, const double *qm, const double *w,
+               const int *flags, long room, double *out) {
+  int nr = g->nr, nth = g->nth, nrn = nr + 1;
+  double a = g->a, rp = 1.0 + sqrt(1.0 - a * a), OmH = a / (2.0 * rp);
+  double *wsum = (double *)calloc((size_t)nr * nth, sizeof(double));
+  for (long k = 0; k < n; ++k) {
+    if (!(flags[k] & OM_ALIVE) || qm[k] == 0.0) continue;
+    int p = om_locate(g->rn, nr + 1, r[k]), q = om_locate(g->tn, nth + 1, th[k]);
+    wsum[(long)q * nr + p] += w[k];
+  }
+  mj_table *T = (mj_table *)malloc(sizeof(mj_table));
+  mj_build(I->theta, T);
+  uint64_t seed = I->seed + event * 0x9E3779B97F4A7C15ULL;
+  long made = 0;
+  for (int q = 0; q < nth; ++q)
+    for (int p = 0; p < nr; ++p) {
+      double rc = g->rh[p], tc = g->th[q];
+      if (rc < I->r0 || rc > I->r1) continue;
+      if (room - made < 2) continue;
+      double sc = om_sqrtg(a, rc, tc);
+      double br = 0.5 * (om_sqrtg(a, g->rn[p], tc) * Br[(long)q * nrn + p] +
+                         om_sqrtg(a, g->rn[p + 1], tc) * Br[(long)q * nrn + p + 1]) / sc;
+      double bt = 0.5 * (om_sqrtg(a, rc, g->tn[q]) * Bt[(long)q * nr + p] +
+                         om_sqrtg(a, rc, g->tn[q + 1]) * Bt[(long)(q + 1) * nr + p]) / sc;
+      double ngj = OmH * fabs(cos(tc) * br - rc * sin(tc) * bt) / (4.0 * M_PI);
+      double V = 2.0 * M_PI * sc * (g->rn[p + 1] - g->rn[p]) * g->dth;
+      long c = (long)q * nr + p;
+      if (!(wsum[c] / V < I->mult * ngj)) continue;
+      double z[3];
+      sample_position(a, seed, c, g->rn[p], g->rn[p + 1], g->tn[q], g->tn[q + 1],
+                      &z[0], &z[1], &z[2]);
+      for (int s = 0; s < 2; ++s) {
+        long id = 2 * c + s;
+        double mag = mj_sample(T, U(seed, id, 200));
+        double mu = 2.0 * U(seed, id, 201) - 1.0;
+        double az = 2.0 * M_PI * U(seed, id, 202);
+        double sn = sqrt(1.0 - mu * mu);
+        double f[3] = {mag * mu, mag * sn * cos(az), mag * sn * sin(az)};
+        double *o = out + 8 * (made + s);
+        o[0] = z[0], o[1] = z[1], o[2] = z[2];
+        fido_to_covariant(a, z[0], z[1], f, &o[3]);
+        o[6] = s == 0 ? 1.0 : -1.0;
+        o[7] = 0.5 * I->density * ngj * V;
+      }
+      made += 2;
+    }
+  free(T);
+  free(wsum);
+  return made;
+}

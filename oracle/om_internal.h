@@ -24,5 +24,7 @@ static inline int om_comp_thalf(int c) {
 }
 
 double om_sqrtg(double a, double r, double th);
+/* cell index lo of v in the increasing table x[0..n-1], clamped to [0, n-2] */
+int om_locate(const double *x, int n, double v);
 
 #endif

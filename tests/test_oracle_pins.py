@@ -826,6 +826,82 @@ def test_poynting_vanishes_for_static_schwarzschild_wald():
     assert vals[1] < vals[0] / 3 or vals[1] < 1e-14
 
 
+# ------------------------------------------------------ pair injection
+def _inj_params(r0=2.0, r1=6.0, mult=3.0, density=5.0, theta=0.5, seed=99):
+    return O.InjectParams(r0, r1, mult, density, theta, seed)
+
+
+def _inj_cells(g, r0, r1):
+    return [(p, q) for q in range(g.nth) for p in range(g.nr) if r0 <= g.rh[p] <= r1]
+
+
+def test_injection_adds_the_goldreich_julian_charge_of_the_volume():
+    """Sec. 3.3 into electrovacuum (the a = 0 Wald start in Kerr): one
+    co-located e+/e- pair per cell of the injection shell, inside its cell,
+    carrying density * n_GJ * V_cell.  For this field Omega . B =
+    Omega_H B0 r^2 sin(theta) / sqrt(g), so the total injected weight is
+    density Omega_H B0 / 2 times the coordinate integral of r^2 sin(theta)
+    over the shell's cells (sqrt(g) cancels); a = 0 injects nothing."""
+    a, B0 = 0.9, 1.0
+    g = O.Grid(a, 48, 40, 1.3, 12.0)
+    D, B = O.wald_grid(g, B0, a_field=0.0)
+    I = _inj_params()
+    q = O.inject(g, I, 0, B, O.Particles(0), 10 ** 6)
+    cells = _inj_cells(g, I.r0, I.r1)
+    assert q.n == 2 * len(cells)
+    assert np.array_equal(q.qm, np.tile([1.0, -1.0], len(cells)))
+    assert np.array_equal(q.r[0::2], q.r[1::2]) and np.array_equal(q.th[0::2], q.th[1::2])
+    for k, (p, qq) in enumerate(cells):
+        assert g.rn[p] <= q.r[2 * k] <= g.rn[p + 1] and g.tn[qq] <= q.th[2 * k] <= g.tn[qq + 1]
+    rp = 1 + np.sqrt(1 - a * a)
+    ps = sorted({p for p, _ in cells})
+    ra, rb = g.rn[ps[0]], g.rn[ps[-1] + 1]
+    shell = (rb ** 3 - ra ** 3) / 3 * 2 * np.cos(g.th0)
+    want = I.density * (a / (2 * rp)) * B0 / 2 * shell
+    assert np.isclose(q.w.sum(), want, rtol=2e-3)
+    g0 = O.Grid(0.0, 48, 40, 2.1, 12.0)
+    D0, B0s = O.wald_grid(g0, B0)
+    assert O.inject(g0, I, 0, B0s, O.Particles(0), 10 ** 6).n == 0
+
+
+def test_injection_stops_at_the_multiplicity_and_respects_room():
+    """A cell holding density * n_GJ >= mult * n_GJ gets no second pair; with
+    mult above density it does.  With room for k pairs the first k eligible
+    cells in index order get them."""
+    a = 0.9
+    g = O.Grid(a, 24, 20, 1.3, 12.0)
+    D, B = O.wald_grid(g, 1.0, a_field=0.0)
+    q1 = O.inject(g, _inj_params(mult=3.0, density=5.0), 0, B, O.Particles(0), 10 ** 6)
+    ncell = len(_inj_cells(g, 2.0, 6.0))
+    assert q1.n == 2 * ncell
+    assert O.inject(g, _inj_params(mult=3.0, density=5.0), 1, B, q1, 10 ** 6).n == q1.n
+    q2 = O.inject(g, _inj_params(mult=10.0, density=5.0), 1, B, q1, 10 ** 6)
+    assert q2.n == 2 * q1.n
+    # the second injection draws from another seed: new positions
+    assert not np.array_equal(q2.r[q1.n:], q1.r)
+    q3 = O.inject(g, _inj_params(), 0, B, O.Particles(0), 11)
+    assert q3.n == 10 and np.array_equal(q3.r, q1.r[:10])
+
+
+def test_injected_momenta_are_maxwell_juettner():
+    """The FIDO Lorentz factors of the injected particles average
+    3 Theta + K_1(1/Theta) / K_2(1/Theta) (relativistic Maxwell-Juettner)."""
+    from scipy.special import kv
+    a = 0.9
+    g = O.Grid(a, 96, 80, 1.3, 12.0)
+    D, B = O.wald_grid(g, 1.0, a_field=0.0)
+    theta = 0.5
+    q = O.inject(g, _inj_params(r0=2.0, r1=10.0, theta=theta), 3, B, O.Particles(0), 10 ** 6)
+    assert q.n > 5000
+    gam = []
+    for z in q.state():
+        m = O.metric(a, z[0], z[1])
+        gi = np.array([[m[6], 0, m[9]], [0, m[7], 0], [m[9], 0, m[8]]])
+        gam.append(np.sqrt(1 + z[3:] @ gi @ z[3:]))
+    want = 3 * theta + kv(1, 1 / theta) / kv(2, 1 / theta)
+    assert abs(np.mean(gam) / want - 1) < 0.02
+
+
 # ------------------------------------------------------------ initial data
 def test_splitmix64_reference_outputs():
     """The counter-based generator is SplitMix64: from state 0 it yields the
