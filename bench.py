@@ -162,7 +162,9 @@ def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
         sort_every=W.get("sort_every", 50),
         push_waves_per_simd=push_wps,
         deposit_mode=G.DEPOSIT_PAPER if W.get("deposit") == "paper" else G.DEPOSIT_CONSERVING,
-        clean_every=W.get("clean_every", 0), clean_iters=W.get("clean_iters", 500))
+        clean_every=W.get("clean_every", 0), clean_iters=W.get("clean_iters", 500),
+        inj_every=W.get("inj_every", 0), inj_r0=rp, inj_r1=6.0, inj_mult=3.0,
+        inj_density=5.0, inj_theta=0.5, inj_seed=SEED + 7)
     if persistent_waves:
         cfg.persistent_waves = persistent_waves
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
@@ -400,6 +402,9 @@ def main():
     ap.add_argument("--clean-every", type=int, default=0,
                     help="divergence cleaning after every N-th step (Sec. 2.4; 0: never)")
     ap.add_argument("--clean-iters", type=int, default=500)
+    ap.add_argument("--inject-every", type=int, default=0,
+                    help="pair injection (Sec. 3.3: r+ <= r <= 6, multiplicity 3, density "
+                         "5 n_GJ, Theta 0.5) after every N-th step (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -427,6 +432,13 @@ def main():
         W["n"] = args.particles
     if args.sort_every:
         W["sort_every"] = args.sort_every
+    if args.inject_every:
+        if W["mode"] != "evolve":
+            print("--inject-every needs a full-cycle workload (c3, c5)", file=sys.stderr)
+            sys.exit(2)
+        W["inj_every"] = args.inject_every
+        W["desc"] += (f"; pair injection every {args.inject_every} steps in r+ <= r <= 6 "
+                      "(multiplicity 3, 5 n_GJ per pair, Theta 0.5)")
     if args.deposit != "conserving" or args.clean_every:
         if W["mode"] != "evolve":
             print("--deposit/--clean-every need a full-cycle workload (c3, c5)", file=sys.stderr)
@@ -470,6 +482,9 @@ def main():
     d1 = ctx.diagnostics()
     tim = ctx.timings()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    if W.get("inj_every"):
+        # injection grows the particle count over the timed steps
+        n_alive = 0.5 * (n_alive + d1["alive"])
     value = n_alive * args.steps / (t1 - t0)
     print(f"[bench] {ms_step:.3f} ms/step, {value:.4e} particle-steps/s", file=sys.stderr,
           flush=True)
@@ -491,7 +506,7 @@ def main():
     bytes_dep = BYTES_DEPOSIT_PAPER if paper else BYTES_DEPOSIT
     # counter summaries are taken on the default configuration of a workload
     wl_key = args.workload + ("_paper" if paper else "") + \
-        ("_clean" if W.get("clean_every") else "")
+        ("_clean" if W.get("clean_every") else "") + ("_inject" if W.get("inj_every") else "")
     if not graph:
         ms = {k: v[0] for k, v in tim.items()
               if k in ("push", "implicit", "deposit", "fields") and v[1] > 0}

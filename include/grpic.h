@@ -144,6 +144,13 @@ typedef struct grpic_config {
   int clean_every;       /* divergence cleaning after every N-th step (0:
                             never; Sec. 2.4 uses 25)                       */
   int clean_iters;       /* Jacobi sweeps per cleaning (Sec. 2.4: 500)     */
+  /* Pair injection (Sec. 3.3), field_mode EVOLVE only; see grpic_inject.  */
+  int inj_every;         /* inject after every N-th step (0: never)        */
+  double inj_r0, inj_r1; /* cells whose centre radius lies in [r0, r1]     */
+  double inj_mult;       /* inject while n < inj_mult * n_GJ (Sec. 3.3: 3) */
+  double inj_density;    /* an injected pair adds inj_density * n_GJ (5)   */
+  double inj_theta;      /* Maxwell-Juettner temperature (0.5)             */
+  uint64_t inj_seed;     /* seed of the injection draws                    */
 } grpic_config;
 
 /* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */
@@ -321,6 +328,24 @@ int grpic_field_diagnostics(grpic_ctx *ctx, double *gauss_max,
  * Allocates the solver's buffers on first use (five FP64 node arrays).
  * GRPIC_E_STATE without field_mode EVOLVE; GRPIC_E_INVALID for iters < 1. */
 int grpic_clean(grpic_ctx *ctx, int iters);
+
+/* ---- pair injection (Sec. 3.3) ---------------------------------------- */
+/* Inject now, as inj_every does after a step: every node cell whose centre
+ * radius lies in [inj_r0, inj_r1] and whose plasma density n (the weights
+ * of its charged particles over V_cell = 2 pi sqrt(g)(centre) dr dtheta)
+ * is below inj_mult * n_GJ receives one co-located e+/e- pair, each
+ * particle of weight inj_density * n_GJ * V_cell / 2, at a position
+ * uniform in proper volume over the cell, with Maxwell-Juettner FIDO
+ * momenta at inj_theta.  n_GJ = Omega_H |cos(theta) B^r - r sin(theta)
+ * B^theta| / (4 pi) at the cell centre from the integer-chain B, Omega_H =
+ * a / (2 r_+).  Cells are taken in index order (theta row, then radius)
+ * while max_particles leaves room for a pair; the new particles take the
+ * next ids.  Draws: SplitMix64 keyed by inj_seed + steps * 0x9E3779B97F4A7C15
+ * (streams: cell index c for the position, 2c and 2c + 1 for the momenta).
+ * *added (may be NULL) receives the number of particles added.
+ * GRPIC_E_STATE without field_mode EVOLVE; GRPIC_E_INVALID for
+ * non-positive inj_mult, inj_density or inj_theta.                        */
+int grpic_inject(grpic_ctx *ctx, long *added);
 
 /* ---- timing ----------------------------------------------------------- */
 enum grpic_kernel_id {

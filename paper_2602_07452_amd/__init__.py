@@ -48,7 +48,9 @@ class Config(C.Structure):
                 ("block", C.c_int), ("persistent_waves", C.c_int),
                 ("push_waves_per_simd", C.c_int), ("dt_implicit", C.c_double),
                 ("t_end", C.c_double), ("deposit_mode", C.c_int), ("clean_every", C.c_int),
-                ("clean_iters", C.c_int)]
+                ("clean_iters", C.c_int), ("inj_every", C.c_int), ("inj_r0", C.c_double),
+                ("inj_r1", C.c_double), ("inj_mult", C.c_double), ("inj_density", C.c_double),
+                ("inj_theta", C.c_double), ("inj_seed", C.c_uint64)]
 
 
 class InitSpec(C.Structure):
@@ -282,6 +284,12 @@ class Context:
                 "reflected": d.reflected, "iter_hist": np.array(d.iter_hist[:]),
                 "herr_hist": np.array(d.herr_hist[:]),
                 "deposit_fallback": d.deposit_fallback}
+
+    def inject(self):
+        """Pair injection now (Sec. 3.3); returns the particles added."""
+        n = C.c_long()
+        self._c("grpic_inject", C.byref(n))
+        return n.value
 
     def clean(self, iters=500):
         """Divergence cleaning of both D chains now (Sec. 2.4)."""

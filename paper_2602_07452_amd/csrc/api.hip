@@ -101,6 +101,11 @@ void validate(const grpic_config& c) {
   if ((c.deposit_mode != GRPIC_DEPOSIT_CONSERVING || c.clean_every > 0) &&
       c.field_mode != GRPIC_FIELDS_EVOLVE)
     bad("deposit_mode and clean_every need field_mode EVOLVE");
+  if (c.inj_every < 0) bad("inj_every must be >= 0");
+  if (c.inj_every > 0 && c.field_mode != GRPIC_FIELDS_EVOLVE)
+    bad("inj_every needs field_mode EVOLVE");
+  if (!(c.inj_mult > 0.0 && c.inj_density > 0.0 && c.inj_theta > 0.0))
+    bad("inj_mult, inj_density and inj_theta must be positive");
   if ((c.dt_implicit > 0.0 && c.dt_implicit != c.dt) || c.t_end > 0.0) {
     if (c.field_mode != GRPIC_FIELDS_NONE)
       bad("steps of their own length and t_end need field_mode NONE");
@@ -319,6 +324,11 @@ void free_all(grpic_ctx* c) {
   for (double* p : {c->clean_kr, c->clean_kt, c->clean_kp, c->clean_src, c->clean_phi[0],
                     c->clean_phi[1]})
     dfree(p);
+  dfree(c->inj_wsum);
+  dfree(c->inj_flag);
+  dfree(c->inj_off);
+  dfree(c->inj_tot);
+  dfree(c->inj_mj);
   dfree(c->acc.Q);
   dfree(c->acc.P);
   dfree(c->acc.Fr);
@@ -382,6 +392,50 @@ void drop_graphs(grpic_ctx* c) {
   }
 }
 
+std::vector<double> mj_table(double theta, int K, double* h_out);
+
+// pair injection after a step or on call; returns the particles added
+long inject_now(grpic_ctx* c) {
+  const long ncell = (long)c->nr * c->nth;
+  if (!c->inj_tot) {
+    long long* wsum = nullptr;
+    int *flag = nullptr, *off = nullptr, *tot = nullptr;
+    double* mj = nullptr;
+    try {
+      wsum = dalloc<long long>(ncell);
+      flag = dalloc<int>(ncell);
+      off = dalloc<int>(ncell);
+      mj = dalloc<double>(kInjMjK + 1);
+      tot = dalloc<int>(4);
+    } catch (...) {
+      dfree(wsum);
+      dfree(flag);
+      dfree(off);
+      dfree(mj);
+      dfree(tot);
+      throw;
+    }
+    double h = 0.0;
+    std::vector<double> C = mj_table(c->cfg.inj_theta, kInjMjK, &h);
+    GRPIC_HIP(hipMemcpy(mj, C.data(), sizeof(double) * (kInjMjK + 1), hipMemcpyHostToDevice));
+    launch_fill(c, wsum, sizeof(long long) * ncell);
+    c->inj_wsum = wsum;
+    c->inj_flag = flag;
+    c->inj_off = off;
+    c->inj_mj = mj;
+    c->inj_mj_h = h;
+    c->inj_tot = tot;
+  }
+  long added = launch_inject(c, c->inj_mj, kInjMjK, c->inj_mj_h);
+  if (added > 0) {
+    // the deposit's fixed-point unit follows the largest weight (the
+    // accumulators are empty between steps); captured steps are stale
+    c->acc.scale = ldexp(1.0, 40) / c->qw_max;
+    drop_graphs(c);
+  }
+  return added;
+}
+
 void run_step(grpic_ctx* c) {
   if (!c->use_graph) {
     step_kernels(c);
@@ -412,6 +466,7 @@ void run_step(grpic_ctx* c) {
   }
   if (c->cfg.clean_every > 0 && c->steps % c->cfg.clean_every == 0)
     launch_clean(c, c->cfg.clean_iters);  // eager, after the step
+  if (c->cfg.inj_every > 0 && c->steps % c->cfg.inj_every == 0) inject_now(c);
   if (c->cfg.sort_every > 0 && c->cfg.field_mode != GRPIC_FIELDS_NONE &&
       c->steps % c->cfg.sort_every == 0)
     launch_sort(c);  // swaps the buffer sets: the other cached graphs apply
@@ -552,6 +607,12 @@ int grpic_config_default(grpic_config* cfg) {
   cfg->deposit_mode = GRPIC_DEPOSIT_CONSERVING;
   cfg->clean_every = 0;
   cfg->clean_iters = 500;
+  cfg->inj_every = 0;
+  cfg->inj_r0 = cfg->inj_r1 = 0.0;
+  cfg->inj_mult = 3.0;
+  cfg->inj_density = 5.0;
+  cfg->inj_theta = 0.5;
+  cfg->inj_seed = 0;
   return GRPIC_OK;
 }
 
@@ -974,6 +1035,16 @@ int grpic_clean(grpic_ctx* c, int iters) {
     if (iters < 1) throw Error(GRPIC_E_INVALID, "iters must be >= 1");
     launch_clean(c, iters);
     GRPIC_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int grpic_inject(grpic_ctx* c, long* added) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (c->cfg.field_mode != GRPIC_FIELDS_EVOLVE)
+      throw Error(GRPIC_E_STATE, "injection needs field_mode EVOLVE");
+    long n = inject_now(c);
+    if (added) *added = n;
   });
 }
 

@@ -129,6 +129,12 @@ struct grpic_ctx {
   // faces, sqrt(g) g^phir on the nodes; the Gauss residual; phi ping-pong
   double *clean_kr = nullptr, *clean_kt = nullptr, *clean_kp = nullptr;
   double *clean_src = nullptr, *clean_phi[2]{};
+  // pair injection (allocated on first use): per node cell weight sums,
+  // eligibility and prefix sums; counters; the Maxwell-Juettner table
+  long long* inj_wsum = nullptr;
+  int *inj_flag = nullptr, *inj_off = nullptr, *inj_tot = nullptr;
+  double* inj_mj = nullptr;
+  double inj_mj_h = 0.0;
   // learned guess
   bool mlp_ready = false;
   void* mlp = nullptr;
@@ -182,6 +188,8 @@ void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,
                            const double* mj_table, int mj_k, double mj_h);
 void launch_energy_H0(grpic_ctx* c);
 void launch_clean(grpic_ctx* c, int iters);  // Sec. 2.4, both D chains
+constexpr int kInjMjK = 4096;                 // intervals of the MJ table
+long launch_inject(grpic_ctx* c, const double* mj, int mj_k, double mj_h);
 void launch_sort(grpic_ctx* c);
 void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,

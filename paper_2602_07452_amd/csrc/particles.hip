@@ -1,17 +1,15 @@
 // particles.hip -- particle initial data, tile sort and small utilities.
 //
-// Initial data: counter-based SplitMix64 draws (Steele, Lea & Flood 2014),
-// draw k of stream s uses counter s * 256 + k.  Positions uniform in proper
-// volume by rejection against r^2 sin(theta) proposals (at most 64 tries),
-// FIDO-frame momenta (isotropic |u| ~ U[0, p0], or Maxwell-Juettner by
-// inverting a tabulated cumulative distribution), mapped to covariant u_i
-// with the Cholesky factor of gamma_ij (order r, theta, phi).
+// Initial data: the seeded draws of sampling_device.hpp (positions uniform
+// in proper volume over a shell; FIDO-frame momenta isotropic with
+// |u| ~ U[0, p0], or Maxwell-Juettner), or circular/eccentric orbits.
 //
 // Tile sort: counting sort of the particles by node-cell tile (32 x 16 cells
 // by default, tiles in serpentine order), dead particles last; keeps a
 // block's particles in a few neighbouring cells for the gather and the
 // deposit.
 #include "deposit_device.hpp"
+#include "sampling_device.hpp"
 
 namespace grpic {
 
@@ -27,19 +25,6 @@ void launch_fill(grpic_ctx* c, void* p, size_t bytes) {
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
                      (uint32_t*)p, n);
   GRPIC_HIP(hipGetLastError());
-}
-
-// ------------------------------------------------------------ SplitMix64
-__device__ __forceinline__ double splitmix_u01(uint64_t seed, uint64_t ctr) {
-  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (double)(z >> 11) * 0x1.0p-53;
-}
-
-__device__ __forceinline__ double draw(uint64_t seed, long stream, int k) {
-  return splitmix_u01(seed, (uint64_t)stream * 256ull + (uint64_t)k);
 }
 
 struct InitArgs {
@@ -73,49 +58,11 @@ __global__ void k_init(InitArgs A) {
     qm = 0;
   } else {
     long pid = (s.kind == GRPIC_INIT_SHELL_MJ) ? id / 2 : id;
-    double C = (1.0 + a * a / (s.r0 * s.r0)) * sqrt(1.0 + 2.0 / s.r0);
-    double c0 = cos(s.t0), c1 = cos(s.t1);
-    double r = s.r0, th = s.t0;
-    double r03 = s.r0 * s.r0 * s.r0, r13 = s.r1 * s.r1 * s.r1;
-    for (int t = 0; t < 64; ++t) {
-      double u1 = draw(s.seed, pid, 3 * t), u2 = draw(s.seed, pid, 3 * t + 1),
-             u3 = draw(s.seed, pid, 3 * t + 2);
-      r = cbrt(r03 + u1 * (r13 - r03));
-      th = acos(c0 - u2 * (c0 - c1));
-      double c = cos(th);
-      double rho2 = r * r + a * a * c * c;
-      double ratio = rho2 / (r * r) * sqrt(1.0 + 2.0 * r / rho2);
-      if (u3 * C < ratio) break;
-    }
-    z[0] = r;
-    z[1] = th;
-    z[2] = 2.0 * kPi * draw(s.seed, pid, 192);
-    double mag;
-    if (s.kind == GRPIC_INIT_SHELL_MJ) {
-      double x = draw(s.seed, id, 200);
-      int lo = 0, hi = A.mj_k;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (A.mj[mid] <= x) lo = mid;
-        else hi = mid;
-      }
-      double dc = A.mj[lo + 1] - A.mj[lo];
-      double f = dc > 0.0 ? (x - A.mj[lo]) / dc : 0.0;
-      mag = (lo + f) * A.mj_h;
-    } else {
-      mag = s.p0 * draw(s.seed, id, 200);
-    }
-    double mu = 2.0 * draw(s.seed, id, 201) - 1.0;
-    double az = 2.0 * kPi * draw(s.seed, id, 202);
-    double sn = sqrt(1.0 - mu * mu);
-    double fr = mag * mu, ft = mag * sn * cos(az), fp = mag * sn * sin(az);
-    Met m;
-    metric(a, r, th, m);
-    double Lrr = sqrt(m.grr), Ltt = sqrt(m.gtt), Lpr = m.grp / Lrr;
-    double Lpp = sqrt(m.gpp - Lpr * Lpr);
-    z[3] = Lrr * fr;
-    z[4] = Ltt * ft;
-    z[5] = Lpr * fr + Lpp * fp;
+    sample_position(a, s.seed, pid, s.r0, s.r1, s.t0, s.t1, z);
+    double mag = s.kind == GRPIC_INIT_SHELL_MJ
+                     ? mj_speed(A.mj, A.mj_k, A.mj_h, draw(s.seed, id, 200))
+                     : s.p0 * draw(s.seed, id, 200);
+    fido_momentum(a, s.seed, id, mag, z[0], z[1], z + 3);
     qm = (id & 1) ? -1 : 1;
   }
   ParticleView& P = A.p;
