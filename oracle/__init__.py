@@ -27,6 +27,7 @@ RK4, IMR, HAM, HYB1, HYB2 = 0, 1, 2, 3, 4
 GUESS_PLAIN, GUESS_RK4, GUESS_EXTERNAL = 0, 1, 2
 FIELDS_NONE, FIELDS_GRID, FIELDS_WALD = 0, 1, 2
 DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
+SOLVER_PICARD, SOLVER_NEWTON = 0, 1
 ALIVE, IMPLICIT, NOCONV, REMOVED, REFLECTED = 1, 2, 4, 8, 16
 NPARAM = 5510
 
@@ -38,15 +39,16 @@ class PushParams(C.Structure):
                 ("r_min", C.c_double), ("r_max", C.c_double),
                 ("th_lo", C.c_double), ("th_hi", C.c_double),
                 ("ham_eps", C.c_double), ("dt_impl", C.c_double), ("t_end", C.c_double),
-                ("deposit_mode", C.c_int)]
+                ("deposit_mode", C.c_int), ("solver", C.c_int)]
 
 
 def push_params(a, dt, pusher=RK4, guess=GUESS_PLAIN, thr=0.0, tol=1e-13,
                 kmax=50, field_kind=FIELDS_NONE, B0=0.0, r_min=0.0,
                 r_max=1e300, th_lo=-1.0, th_hi=10.0, ham_eps=1e-10, dt_impl=0.0,
-                t_end=0.0, deposit_mode=DEPOSIT_CONSERVING):
+                t_end=0.0, deposit_mode=DEPOSIT_CONSERVING, solver=SOLVER_PICARD):
     return PushParams(a, dt, pusher, guess, thr, tol, kmax, field_kind, B0,
-                      r_min, r_max, th_lo, th_hi, ham_eps, dt_impl, t_end, deposit_mode)
+                      r_min, r_max, th_lo, th_hi, ham_eps, dt_impl, t_end, deposit_mode,
+                      solver)
 
 
 class _OmParticles(C.Structure):

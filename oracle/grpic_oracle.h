@@ -83,6 +83,7 @@ enum { OM_RK4 = 0, OM_IMR = 1, OM_HAM = 2, OM_HYB1 = 3, OM_HYB2 = 4 };
 enum { OM_GUESS_PLAIN = 0, OM_GUESS_RK4 = 1, OM_GUESS_EXTERNAL = 2 };
 enum { OM_FIELDS_NONE = 0, OM_FIELDS_GRID = 1, OM_FIELDS_WALD = 2 };
 enum { OM_DEPOSIT_CONSERVING = 0, OM_DEPOSIT_PAPER = 1 };
+enum { OM_SOLVER_PICARD = 0, OM_SOLVER_NEWTON = 1 };
 enum {
   OM_ALIVE = 1,
   OM_IMPLICIT = 2,
@@ -107,6 +108,7 @@ typedef struct {
   double t_end;     /* with particle clocks: steps are clipped to end at
                        t_end and particles that reached it stay (0: none) */
   int deposit_mode; /* OM_DEPOSIT_CONSERVING or OM_DEPOSIT_PAPER (pic step) */
+  int solver;       /* implicit midpoint: OM_SOLVER_PICARD or _NEWTON      */
 } om_push_params;
 
 typedef struct {

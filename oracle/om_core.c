@@ -254,11 +254,75 @@ static int converged(const double *znew, const double *zold, double tol) {
  * (Picard) iteration  z[k] = z^n + dt F((z^n + z[k-1])/2)  from a guess.
  * Returns the iteration count (negative if the cap was reached).
  * ------------------------------------------------------------------------ */
+/* Newton's method on the same equation, the solver the paper names (the
+ * Picard iteration above is the default reading):
+ *   G(y) = y - z - dt F((z + y)/2),  J = I - (dt/2) dF/dx at the midpoint,
+ * dF/dx by forward differences with steps h_j = 2^-26 max(|m_j|, 1) (the
+ * step actually taken, (m_j + h_j) - m_j, divides), y <- y - J^{-1} G(y)
+ * by Gaussian elimination with partial pivoting.  Same stopping test and
+ * cap as the Picard iteration; Wq from the last midpoint evaluation.      */
+static int imr_newton(const om_push_params *P, const om_grid *g,
+                      const double *const *G, double qm, const double *z,
+                      double *zk, double *Wq) {
+  double pw = 0.0;
+  for (int k = 1; k <= P->kmax; ++k) {
+    double m[6], f0[6], A[6][7];
+    for (int i = 0; i < 6; ++i) m[i] = 0.5 * (z[i] + zk[i]);
+    eval_rhs(P, g, G, qm, m, f0, &pw);
+    for (int j = 0; j < 6; ++j) {
+      double mj[6], fj[6], pj;
+      memcpy(mj, m, sizeof(mj));
+      double h = 0x1p-26 * (fabs(m[j]) > 1.0 ? fabs(m[j]) : 1.0);
+      mj[j] = m[j] + h;
+      h = mj[j] - m[j];
+      eval_rhs(P, g, G, qm, mj, fj, &pj);
+      for (int i = 0; i < 6; ++i)
+        A[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * P->dt * (fj[i] - f0[i]) / h;
+    }
+    for (int i = 0; i < 6; ++i) A[i][6] = -(zk[i] - z[i] - P->dt * f0[i]);
+    for (int c = 0; c < 6; ++c) { /* elimination with partial pivoting */
+      int piv = c;
+      for (int i = c + 1; i < 6; ++i)
+        if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
+      if (piv != c)
+        for (int j = c; j < 7; ++j) {
+          double t = A[c][j];
+          A[c][j] = A[piv][j];
+          A[piv][j] = t;
+        }
+      for (int i = c + 1; i < 6; ++i) {
+        double l = A[i][c] / A[c][c];
+        for (int j = c; j < 7; ++j) A[i][j] -= l * A[c][j];
+      }
+    }
+    double dy[6], zn[6];
+    for (int i = 5; i >= 0; --i) {
+      double v = A[i][6];
+      for (int j = i + 1; j < 6; ++j) v -= A[i][j] * dy[j];
+      dy[i] = v / A[i][i];
+    }
+    for (int i = 0; i < 6; ++i) zn[i] = zk[i] + dy[i];
+    int c = converged(zn, zk, P->tol);
+    memcpy(zk, zn, sizeof(zn));
+    if (c) {
+      if (Wq) *Wq = P->dt * pw;
+      return k;
+    }
+  }
+  if (Wq) *Wq = P->dt * pw;
+  return -P->kmax;
+}
+
 int om_step_imr(const om_push_params *P, const om_grid *g,
                 const double *const *G, double qm, const double *z,
                 const double *guess, double *out, double *Wq) {
   double zk[6], zm[6], f[6], zn[6], pw = 0.0;
   memcpy(zk, guess ? guess : z, sizeof(zk));
+  if (P->solver == OM_SOLVER_NEWTON) {
+    int it = imr_newton(P, g, G, qm, z, zk, Wq);
+    memcpy(out, zk, sizeof(zk));
+    return it;
+  }
   for (int k = 1; k <= P->kmax; ++k) {
     for (int i = 0; i < 6; ++i) zm[i] = 0.5 * (z[i] + zk[i]);
     eval_rhs(P, g, G, qm, zm, f, &pw);

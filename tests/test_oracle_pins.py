@@ -419,6 +419,34 @@ def test_charged_energy_budget_residual_is_rk4_local_error():
     assert 20 < vals[0] / vals[1] < 45
 
 
+@pytest.mark.parametrize("dt", [0.05, 0.5, 1.0])
+def test_newton_solves_the_same_midpoint_equation(dt):
+    """The implicit midpoint equation (eq. imr1) has one solution near z^n:
+    Newton's method (the solver Sec. 2.2.2 names) and the Picard iteration
+    reach it to the stopping tolerance; Newton converges quadratically, in
+    at most five iterations, where Picard needs many more as dt grows."""
+    a, B0 = 0.9, 1.0
+    rng = np.random.default_rng(31)
+    kw = dict(field_kind=O.FIELDS_WALD, B0=B0, kmax=200, tol=1e-13)
+    itp, itn = [], []
+    for _ in range(12):
+        z = np.array([rng.uniform(3, 12), rng.uniform(0.4, 2.7), 0.3, rng.normal(),
+                      rng.normal(), rng.normal() * 2])
+        qm = rng.choice([-1.0, 1.0])
+        zp, ip, Wp = O.step_imr(O.push_params(a, dt, **kw), qm, z)
+        zn, inn, Wn = O.step_imr(O.push_params(a, dt, solver=O.SOLVER_NEWTON, **kw), qm, z)
+        assert ip > 0 and inn > 0
+        assert np.all(np.abs(zp - zn) <= 2e-12 * np.maximum(np.abs(zp), 1))
+        # the solution satisfies eq. imr1 itself
+        f = O.rhs(a, qm, 0.5 * (z + zn), *O.wald_fields(a, B0, *(0.5 * (z + zn))[:2]))
+        assert np.all(np.abs(zn - z - dt * f) <= 1e-12 * np.maximum(np.abs(zn), 1))
+        itp.append(ip)
+        itn.append(inn)
+    assert max(itn) <= 5
+    if dt >= 0.5:
+        assert np.mean(itp) > 2.5 * np.mean(itn)
+
+
 # --------------------------------------- own step lengths (Sec. 3.1.2, Table 2)
 def _clocked(p):
     p = p.copy()
