@@ -72,6 +72,12 @@ enum grpic_field_mode {
   GRPIC_FIELDS_EVOLVE = 2  /* full PIC step: Maxwell + gather + push +
                               deposit                                      */
 };
+enum grpic_solver {
+  GRPIC_SOLVER_PICARD = 0, /* fixed-point iteration of eq. imr1 (default)  */
+  GRPIC_SOLVER_NEWTON = 1  /* Newton's method (Sec. 2.2.2): forward-
+                              difference Jacobian of the midpoint map,
+                              Gaussian elimination with partial pivoting   */
+};
 enum grpic_deposit_mode {
   GRPIC_DEPOSIT_CONSERVING = 0, /* charge-conserving face fluxes over the
                                    move (default); J^{n+3/2} in sub-step 8,
@@ -151,6 +157,7 @@ typedef struct grpic_config {
   double inj_density;    /* an injected pair adds inj_density * n_GJ (5)   */
   double inj_theta;      /* Maxwell-Juettner temperature (0.5)             */
   uint64_t inj_seed;     /* seed of the injection draws                    */
+  int solver;            /* implicit midpoint: enum grpic_solver           */
 } grpic_config;
 
 /* Fill *cfg with defaults (no grid, RK4, dt = 0.01, tol 1e-13, kmax 50).  */

@@ -27,6 +27,7 @@ FLAG_ALIVE, FLAG_IMPLICIT, FLAG_NOCONV, FLAG_REMOVED, FLAG_REFLECTED = 1, 2, 4, 
 K_FIELDS, K_PUSH, K_IMPLICIT, K_DEPOSIT, K_SORT, K_GUESS, K_CLEAN = range(7)
 KERNEL_NAMES = ("fields", "push", "implicit", "deposit", "sort", "guess", "clean")
 DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
+SOLVER_PICARD, SOLVER_NEWTON = 0, 1
 HIST_BINS = 64
 MLP_NPARAM = 5510
 
@@ -50,7 +51,7 @@ class Config(C.Structure):
                 ("t_end", C.c_double), ("deposit_mode", C.c_int), ("clean_every", C.c_int),
                 ("clean_iters", C.c_int), ("inj_every", C.c_int), ("inj_r0", C.c_double),
                 ("inj_r1", C.c_double), ("inj_mult", C.c_double), ("inj_density", C.c_double),
-                ("inj_theta", C.c_double), ("inj_seed", C.c_uint64)]
+                ("inj_theta", C.c_double), ("inj_seed", C.c_uint64), ("solver", C.c_int)]
 
 
 class InitSpec(C.Structure):

@@ -101,6 +101,8 @@ void validate(const grpic_config& c) {
   if ((c.deposit_mode != GRPIC_DEPOSIT_CONSERVING || c.clean_every > 0) &&
       c.field_mode != GRPIC_FIELDS_EVOLVE)
     bad("deposit_mode and clean_every need field_mode EVOLVE");
+  if (c.solver != GRPIC_SOLVER_PICARD && c.solver != GRPIC_SOLVER_NEWTON)
+    bad("unknown solver");
   if (c.inj_every < 0) bad("inj_every must be >= 0");
   if (c.inj_every > 0 && c.field_mode != GRPIC_FIELDS_EVOLVE)
     bad("inj_every needs field_mode EVOLVE");

@@ -217,6 +217,72 @@ __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, dou
   return -A.kmax;
 }
 
+// Newton's method on the same equation (the solver the paper names; the
+// Picard iteration above is the default): G(y) = y - z - dt F((z + y)/2),
+// J = I - (dt/2) dF/dx at the midpoint by forward differences with steps
+// 2^-26 max(|m_j|, 1) (the step taken, (m_j + h) - m_j, divides), then
+// y -= J^{-1} G(y) by Gaussian elimination with partial pivoting; same
+// stopping test; Wq from the last midpoint evaluation
+template <bool GRID>
+__device__ int imr_newton(const PushArgs& A, double dt, double qm, const double* z,
+                          double s0, double c0, double* zk, double* Wq) {
+  double p = 0.0;
+  for (int k = 1; k <= A.kmax; ++k) {
+    double m[6], f0[6], J[6][7], sm, cm;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) m[i] = 0.5 * (z[i] + zk[i]);
+    sincos_near(m[1], z[1], s0, c0, &sm, &cm);
+    eval<GRID>(A, qm, m, sm, cm, f0, &p);
+#pragma unroll 1
+    for (int j = 0; j < 6; ++j) {
+      double mj[6], fj[6], pj, sj, cj;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) mj[i] = m[i];
+      double h = 0x1p-26 * fmax(fabs(m[j]), 1.0);
+      mj[j] = m[j] + h;
+      h = mj[j] - m[j];
+      sincos_near(mj[1], z[1], s0, c0, &sj, &cj);
+      eval<GRID>(A, qm, mj, sj, cj, fj, &pj);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) J[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * dt * (fj[i] - f0[i]) / h;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) J[i][6] = -(zk[i] - z[i] - dt * f0[i]);
+    for (int c = 0; c < 6; ++c) {
+      int piv = c;
+      for (int i = c + 1; i < 6; ++i)
+        if (fabs(J[i][c]) > fabs(J[piv][c])) piv = i;
+      if (piv != c)
+        for (int j = c; j < 7; ++j) {
+          double t = J[c][j];
+          J[c][j] = J[piv][j];
+          J[piv][j] = t;
+        }
+      for (int i = c + 1; i < 6; ++i) {
+        double l = J[i][c] / J[c][c];
+        for (int j = c; j < 7; ++j) J[i][j] -= l * J[c][j];
+      }
+    }
+    double dy[6], zn[6];
+    for (int i = 5; i >= 0; --i) {
+      double v = J[i][6];
+      for (int j = i + 1; j < 6; ++j) v -= J[i][j] * dy[j];
+      dy[i] = v / J[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zn[i] = zk[i] + dy[i];
+    bool cv = small_change(zn, zk, A.tol);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zk[i] = zn[i];
+    if (cv) {
+      *Wq = dt * p;
+      return k;
+    }
+  }
+  *Wq = dt * p;
+  return -A.kmax;
+}
+
 // ------------------------------------------- discrete-gradient scheme (DG)
 // Variables 0 r, 1 theta, 2 phi, 3 u_r, 4 u_theta, 5 u_phi.  Six orderings
 // (three cyclic orders with x before u and their reverses); at most four
@@ -504,7 +570,7 @@ void k_push_explicit(PushArgs A) {
 // ------------------------------------------------------- implicit pass
 constexpr unsigned kGrab = 64;  // queue entries a wave takes at a time
 
-template <bool GRID, bool EVOLVE, bool HAM>
+template <bool GRID, bool EVOLVE, bool HAM, bool NEWTON>
 __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
   __shared__ LocalStats ls;
   __shared__ unsigned pref[kQueueSegs + 1];
@@ -546,12 +612,20 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       }
       double Wq = 0.0, s0, c0;
       fsincos(z[1], &s0, &c0);
-      int it = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+      int it;
+      if constexpr (NEWTON)
+        it = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+      else
+        it = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
       if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
         // no convergence from the learned guess: restart from z^n
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = z[i];
-        int it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+        int it2;
+        if constexpr (NEWTON)
+          it2 = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+        else
+          it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
         it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
       }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
@@ -651,12 +725,21 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   time_begin(c, GRPIC_K_IMPLICIT, &ev);
   // the discrete-gradient code is only compiled into the variant used when
   // neutral particles are present (it needs many more registers)
-  if (c->has_neutral && c->cfg.pusher != GRPIC_PUSH_IMR)
-    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, true>), dim3(blocks), dim3(256), 0,
-                       c->stream, A);
-  else
-    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, false>), dim3(blocks), dim3(256), 0,
-                       c->stream, A);
+  const bool ham = c->has_neutral && c->cfg.pusher != GRPIC_PUSH_IMR;
+  if (c->cfg.solver == GRPIC_SOLVER_NEWTON) {
+    if (ham)
+      hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, true, true>), dim3(blocks),
+                         dim3(256), 0, c->stream, A);
+    else
+      hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, false, true>), dim3(blocks),
+                         dim3(256), 0, c->stream, A);
+  } else if (ham) {
+    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, true, false>), dim3(blocks), dim3(256),
+                       0, c->stream, A);
+  } else {
+    hipLaunchKernelGGL((k_push_implicit<GRID, EVOLVE, false, false>), dim3(blocks),
+                       dim3(256), 0, c->stream, A);
+  }
   GRPIC_HIP(hipGetLastError());
   time_end(c, GRPIC_K_IMPLICIT, ev);
   if (collect) mlp_collect_advance(c);

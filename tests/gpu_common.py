@@ -58,7 +58,8 @@ def push_params_from(cfg, field_kind):
                          r_max=cfg.r_remove_out,
                          th_lo=cfg.theta0 if cfg.reflect else -1.0,
                          th_hi=np.pi - cfg.theta0 if cfg.reflect else 10.0,
-                         ham_eps=cfg.ham_eps, dt_impl=cfg.dt_implicit, t_end=cfg.t_end)
+                         ham_eps=cfg.ham_eps, dt_impl=cfg.dt_implicit, t_end=cfg.t_end,
+                         deposit_mode=cfg.deposit_mode, solver=cfg.solver)
 
 
 def compare_push(cfg, before, after, P, grid=None, G6=None, tol=TOL_STATE, t=None):

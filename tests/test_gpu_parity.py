@@ -172,6 +172,49 @@ def test_charged_static_wald_one_step(pusher, thr, guess):
         assert 0.0 < frac < 1.0
 
 
+@pytest.mark.parametrize("pusher,thr", [(G.PUSH_IMR, 0.0), (G.PUSH_HYB2, 1e-13)])
+def test_newton_solver_matches_oracle_and_picard(pusher, thr):
+    """Newton's method (solver NEWTON) against the oracle's Newton, and the
+    same solution as the Picard iteration in fewer iterations (dt = 0.1)."""
+    out = {}
+    for solver in (G.SOLVER_NEWTON, G.SOLVER_PICARD):
+        cfg = _wald_cfg(pusher, thr, dt=0.1)
+        cfg.solver = solver
+        g = oracle_grid(cfg)
+        with G.Context(cfg) as ctx:
+            ctx.set_fields_wald(1.0)
+            ctx.init_particles(G.INIT_SHELL_ISO, cfg.max_particles, SEED + 2, 2.0, 30.0,
+                               cfg.theta0, np.pi - cfg.theta0, 1.0)
+            G6 = gpu_fields_as_G(ctx)
+            before = ctx.get_particles()
+            ctx.step(1)
+            after = ctx.get_particles()
+        if solver == G.SOLVER_NEWTON:
+            err, _ = compare_push(cfg, before, after, push_params_from(cfg, O.FIELDS_GRID),
+                                  grid=g, G6=G6)
+            assert err <= TOL_STATE
+        out[solver] = after
+    n, p = out[G.SOLVER_NEWTON], out[G.SOLVER_PICARD]
+    both = ((n["flags"] & p["flags"] & G.FLAG_IMPLICIT) != 0)
+    assert both.sum() > 100
+    assert np.all(state_err(n["z"][both], p["z"][both]) <= 2e-12)
+    assert n["iters"][both].mean() < 0.7 * p["iters"][both].mean()
+
+
+def test_newton_solver_neutral_orbits(orbits):
+    """The implicit midpoint rule by Newton's method for geodesics."""
+    cfg0, P0 = orbits
+    cfg = G.config_default(a=0.0, dt=0.05, max_particles=len(P0["r"]), pusher=G.PUSH_IMR,
+                           r_remove_in=2.0, solver=G.SOLVER_NEWTON)
+    with G.Context(cfg) as ctx:
+        ctx.load_particles(P0["z"], P0["qm"], P0["w"], H0=P0["H0"])
+        before = ctx.get_particles()
+        ctx.step(1)
+        after = ctx.get_particles()
+    err, _ = compare_push(cfg, before, after, push_params_from(cfg, O.FIELDS_NONE))
+    assert err <= TOL_STATE
+
+
 def test_shell_initial_data_matches_oracle():
     cfg = _wald_cfg(G.PUSH_RK4, n=2000)
     with G.Context(cfg) as ctx:
