@@ -36,6 +36,9 @@ FLOP_EVAL = FLOP_METRIC_D + FLOP_GATHER + FLOP_RHS
 FLOP_RK4 = 4 * FLOP_EVAL + FLOP_RK4_COMB
 FLOP_SWITCH = 2 * FLOP_ENERGY + 4
 FLOP_IMR_ITER = FLOP_EVAL + FLOP_IMR_EXTRA
+# Newton (solver "newton"): the base and six perturbed evaluations, the 6 x 6
+# Jacobian (108), elimination with pivoting and back substitution (~220)
+FLOP_NEWTON_EXTRA = 108 + 220 + FLOP_IMR_EXTRA
 # algorithmic HBM bytes per particle of the explicit push pass: state in/out
 # (2 x 48), q/m, flags, H0, herr in/out, iterations, old position + dphi,
 # new weights (three stored, the fourth is their complement) + cell
@@ -164,7 +167,8 @@ def make_context(G, W, n=None, push_wps=0, persistent_waves=0):
         deposit_mode=G.DEPOSIT_PAPER if W.get("deposit") == "paper" else G.DEPOSIT_CONSERVING,
         clean_every=W.get("clean_every", 0), clean_iters=W.get("clean_iters", 500),
         inj_every=W.get("inj_every", 0), inj_r0=rp, inj_r1=6.0, inj_mult=3.0,
-        inj_density=5.0, inj_theta=0.5, inj_seed=SEED + 7)
+        inj_density=5.0, inj_theta=0.5, inj_seed=SEED + 7,
+        solver=G.SOLVER_NEWTON if W.get("solver") == "newton" else G.SOLVER_PICARD)
     if persistent_waves:
         cfg.persistent_waves = persistent_waves
     cfg.dt = 0.5 * G.cfl_dt(cfg) if evolve else W["dt"]
@@ -402,6 +406,8 @@ def main():
     ap.add_argument("--clean-every", type=int, default=0,
                     help="divergence cleaning after every N-th step (Sec. 2.4; 0: never)")
     ap.add_argument("--clean-iters", type=int, default=500)
+    ap.add_argument("--solver", choices=("picard", "newton"), default="picard",
+                    help="implicit midpoint solver (Newton: Sec. 2.2.2)")
     ap.add_argument("--inject-every", type=int, default=0,
                     help="pair injection (Sec. 3.3: r+ <= r <= 6, multiplicity 3, density "
                          "5 n_GJ, Theta 0.5) after every N-th step (0: never)")
@@ -432,6 +438,9 @@ def main():
         W["n"] = args.particles
     if args.sort_every:
         W["sort_every"] = args.sort_every
+    if args.solver != "picard":
+        W["solver"] = args.solver
+        W["desc"] += f"; {args.solver} solver for the implicit midpoint rule"
     if args.inject_every:
         if W["mode"] != "evolve":
             print("--inject-every needs a full-cycle workload (c3, c5)", file=sys.stderr)
@@ -495,7 +504,9 @@ def main():
     evolve = W["mode"] == "evolve"
     grid = W["mode"] != "none"
     flop_rk4 = FLOP_RK4 if grid else FLOP_RK4 - 4 * FLOP_GATHER
-    flop_iter = FLOP_IMR_ITER if grid else FLOP_IMR_ITER - FLOP_GATHER
+    n_eval = 7 if W.get("solver") == "newton" else 1
+    flop_iter = n_eval * (FLOP_EVAL if grid else FLOP_EVAL - FLOP_GATHER) + \
+        (FLOP_NEWTON_EXTRA if n_eval > 1 else FLOP_IMR_EXTRA)
     flops = {
         "push": args.steps * n_alive * (flop_rk4 + FLOP_SWITCH) +
         (args.steps * n_alive - impl) * (FLOP_WEIGHTS if evolve else 0),
@@ -506,7 +517,8 @@ def main():
     bytes_dep = BYTES_DEPOSIT_PAPER if paper else BYTES_DEPOSIT
     # counter summaries are taken on the default configuration of a workload
     wl_key = args.workload + ("_paper" if paper else "") + \
-        ("_clean" if W.get("clean_every") else "") + ("_inject" if W.get("inj_every") else "")
+        ("_clean" if W.get("clean_every") else "") + ("_inject" if W.get("inj_every") else "") + \
+        ("_newton" if W.get("solver") == "newton" else "")
     if not graph:
         ms = {k: v[0] for k, v in tim.items()
               if k in ("push", "implicit", "deposit", "fields") and v[1] > 0}
