@@ -115,7 +115,8 @@ typedef struct grpic_config {
   int nr, nth;           /* grid cells (ignored for GRPIC_FIELDS_NONE)      */
   double r_in, r_out;    /* radial extent of the grid                       */
   double theta0;         /* theta edges at theta0, pi - theta0 (Sec. 2.5)   */
-  double dt;             /* time step                                       */
+  double dt;             /* time step (0 with a grid: half the Courant
+                            limit, see grpic_cfl_dt)                       */
   int field_mode;        /* enum grpic_field_mode                           */
   int pusher;            /* enum grpic_pusher                               */
   int guess;             /* enum grpic_guess                                */
@@ -171,6 +172,9 @@ typedef struct grpic_ctx grpic_ctx;
  * grid's Courant limit for field_mode EVOLVE), GRPIC_E_OOM, GRPIC_E_HIP,
  * GRPIC_E_NODEVICE.  *out is NULL on failure.                             */
 int grpic_create(const grpic_config *cfg, grpic_ctx **out);
+/* The context's configuration as it is now: dt resolved, and the launch
+ * settings grpic_autotune may have changed.                               */
+int grpic_get_config(grpic_ctx *ctx, grpic_config *out);
 void grpic_destroy(grpic_ctx *ctx);
 /* Message of the last failing call on ctx (ctx may be NULL: last failure
  * of grpic_create).  Owned by the library.                                */

@@ -124,10 +124,16 @@ class Context:
     """One GRPIC simulation context on the current HIP device."""
 
     def __init__(self, cfg: Config):
-        self.cfg = cfg
         h = C.c_void_p()
         _check(lib().grpic_create(C.byref(cfg), C.byref(h)))
         self._h = h
+        self.cfg = self.get_config()  # dt resolved (0: half the Courant limit)
+
+    def get_config(self) -> Config:
+        """The configuration as the library holds it now."""
+        out = Config()
+        self._c("grpic_get_config", C.byref(out))
+        return out
 
     # -- lifetime
     def close(self):

@@ -631,6 +631,12 @@ int grpic_create(const grpic_config* cfg, grpic_ctx** out) {
   *out = nullptr;
   grpic_ctx* c = nullptr;
   try {
+    grpic_config cf = *cfg;
+    // dt = 0 with a grid: half the Courant limit
+    if (cf.dt == 0.0 && cf.field_mode != GRPIC_FIELDS_NONE && cf.nr >= 2 && cf.nth >= 2 &&
+        cf.r_in > 0.0 && cf.r_out > cf.r_in && cf.theta0 > 0.0 && cf.theta0 < 0.5 * kPi)
+      cf.dt = 0.5 * cfl_limit(cf);
+    cfg = &cf;
     validate(*cfg);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -697,6 +703,14 @@ const char* grpic_last_error(const grpic_ctx* c) {
   if (c) return c->err.c_str();
   std::lock_guard<std::mutex> lk(g_err_mu);
   return g_create_err.c_str();
+}
+
+int grpic_get_config(grpic_ctx* c, grpic_config* out) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!out) throw Error(GRPIC_E_INVALID, "null pointer");
+    *out = c->cfg;
+  });
 }
 
 int grpic_set_stream(grpic_ctx* c, void* s) {

@@ -190,3 +190,18 @@ def test_schwarzschild_wald_start_full_steps():
          [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
     err, _ = compare_push(cfg, P0, P1, push_params_from(cfg, O.FIELDS_GRID), grid=g, G6=G6)
     assert err <= TOL_STATE
+
+
+def test_zero_dt_is_half_the_courant_limit():
+    """dt = 0 with a grid resolves to half the Courant limit (grpic_cfl_dt);
+    the context reports the resolved configuration."""
+    cfg = _pic_cfg(n=64)
+    want = 0.5 * G.cfl_dt(cfg)
+    cfg.dt = 0.0
+    with G.Context(cfg) as ctx:
+        assert ctx.cfg.dt == want and ctx.get_config().dt == want
+        ctx.set_fields_wald(1.0)
+        ctx.step(1)
+    cfg = G.config_default(a=0.0, dt=0.0, max_particles=8)  # no grid: dt needed
+    with pytest.raises(G.GrpicError):
+        G.Context(cfg)
