@@ -108,6 +108,8 @@ enum grpic_level {
 #define GRPIC_FLAG_NOCONV 4    /* implicit iteration hit kmax              */
 #define GRPIC_FLAG_REMOVED 8   /* left the domain in the last step         */
 #define GRPIC_FLAG_REFLECTED 16 /* reflected at a theta edge last step     */
+#define GRPIC_FLAG_NONFINITE 32 /* the step gave a non-finite state: the
+                                   particle was removed (with REMOVED)     */
 
 /* ---- configuration ---------------------------------------------------- */
 typedef struct grpic_config {
@@ -321,6 +323,8 @@ typedef struct grpic_diag {
                                       [10^(b/2-30), 10^((b+1)/2-30))       */
   long deposit_fallback; /* deposit blocks whose node box did not fit the
                             on-chip bins (cumulative)                      */
+  long nonfinite;        /* particles removed for a non-finite state
+                            (cumulative, also counted in removed)          */
 } grpic_diag;
 int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
 /* Grid diagnostics on the integer chain: max |Gauss residual| over interior

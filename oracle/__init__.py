@@ -28,7 +28,7 @@ GUESS_PLAIN, GUESS_RK4, GUESS_EXTERNAL = 0, 1, 2
 FIELDS_NONE, FIELDS_GRID, FIELDS_WALD = 0, 1, 2
 DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
 SOLVER_PICARD, SOLVER_NEWTON = 0, 1
-ALIVE, IMPLICIT, NOCONV, REMOVED, REFLECTED = 1, 2, 4, 8, 16
+ALIVE, IMPLICIT, NOCONV, REMOVED, REFLECTED, NONFINITE = 1, 2, 4, 8, 16, 32
 NPARAM = 5510
 
 

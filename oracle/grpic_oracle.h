@@ -89,7 +89,8 @@ enum {
   OM_IMPLICIT = 2,
   OM_NOCONV = 4,
   OM_REMOVED = 8,
-  OM_REFLECTED = 16
+  OM_REFLECTED = 16,
+  OM_NONFINITE = 32 /* non-finite state after the step (with OM_REMOVED) */
 };
 
 typedef struct {

@@ -579,8 +579,13 @@ static void push_one(const om_push_params *P0, const om_grid *g,
     if (it < 0) fl |= OM_NOCONV, it = -it;
   }
   herr_new = crit_value(P, qm, p->H0[k], z, out, Wq);
-  /* particle boundary conditions (Sec. 2.5) */
-  if (out[0] < P->r_min || out[0] > P->r_max) {
+  /* a state that is no number takes the particle out of the run; then the
+   * particle boundary conditions (Sec. 2.5) */
+  int finite = 1;
+  for (int i = 0; i < 6; ++i) finite = finite && isfinite(out[i]);
+  if (!finite) {
+    fl = OM_REMOVED | OM_NONFINITE;
+  } else if (out[0] < P->r_min || out[0] > P->r_max) {
     fl = (fl & ~OM_ALIVE) | OM_REMOVED;
   } else if (P->th_lo >= 0.0) {
     if (out[1] < P->th_lo) {

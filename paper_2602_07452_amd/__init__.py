@@ -24,6 +24,7 @@ FIELDS_NONE, FIELDS_STATIC, FIELDS_EVOLVE = 0, 1, 2
 LEVEL_DN, LEVEL_DH0, LEVEL_DH1, LEVEL_BM, LEVEL_BN, LEVEL_BH, LEVEL_J, LEVEL_JPREV = range(8)
 INIT_ORBITS, INIT_SHELL_ISO, INIT_SHELL_MJ = 0, 1, 2
 FLAG_ALIVE, FLAG_IMPLICIT, FLAG_NOCONV, FLAG_REMOVED, FLAG_REFLECTED = 1, 2, 4, 8, 16
+FLAG_NONFINITE = 32
 K_FIELDS, K_PUSH, K_IMPLICIT, K_DEPOSIT, K_SORT, K_GUESS, K_CLEAN = range(7)
 KERNEL_NAMES = ("fields", "push", "implicit", "deposit", "sort", "guess", "clean")
 DEPOSIT_CONSERVING, DEPOSIT_PAPER = 0, 1
@@ -64,7 +65,8 @@ class Diag(C.Structure):
     _fields_ = [("steps", C.c_long), ("alive", C.c_long), ("removed", C.c_long),
                 ("implicit_steps", C.c_long), ("noconv", C.c_long),
                 ("reflected", C.c_long), ("iter_hist", C.c_long * HIST_BINS),
-                ("herr_hist", C.c_long * HIST_BINS), ("deposit_fallback", C.c_long)]
+                ("herr_hist", C.c_long * HIST_BINS), ("deposit_fallback", C.c_long),
+                ("nonfinite", C.c_long)]
 
 
 def lib():
@@ -290,7 +292,7 @@ class Context:
                 "implicit_steps": d.implicit_steps, "noconv": d.noconv,
                 "reflected": d.reflected, "iter_hist": np.array(d.iter_hist[:]),
                 "herr_hist": np.array(d.herr_hist[:]),
-                "deposit_fallback": d.deposit_fallback}
+                "deposit_fallback": d.deposit_fallback, "nonfinite": d.nonfinite}
 
     def inject(self):
         """Pair injection now (Sec. 3.3); returns the particles added."""

@@ -1025,6 +1025,7 @@ int grpic_get_diagnostics(grpic_ctx* c, grpic_diag* out) {
       out->implicit_steps += (long)r.implicit_steps;
       out->noconv += (long)r.noconv;
       out->reflected += (long)r.reflected;
+      out->nonfinite += (long)r.nonfinite;
       for (int i = 0; i < GRPIC_HIST_BINS; ++i) {
         out->iter_hist[i] += (long)r.iter_hist[i];
         out->herr_hist[i] += (long)r.herr_hist[i];

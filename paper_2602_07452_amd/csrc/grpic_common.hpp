@@ -44,7 +44,8 @@ struct StatRep {
   unsigned long long implicit_steps, noconv, removed, reflected, alive;
   unsigned long long iter_hist[kHistBins];
   unsigned long long herr_hist[kHistBins];
-  unsigned long long pad[3];
+  unsigned long long nonfinite;
+  unsigned long long pad[2];
 };
 
 struct Stats {

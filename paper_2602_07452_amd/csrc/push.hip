@@ -22,7 +22,8 @@ enum : uint8_t {
   F_IMPLICIT = GRPIC_FLAG_IMPLICIT,
   F_NOCONV = GRPIC_FLAG_NOCONV,
   F_REMOVED = GRPIC_FLAG_REMOVED,
-  F_REFLECTED = GRPIC_FLAG_REFLECTED
+  F_REFLECTED = GRPIC_FLAG_REFLECTED,
+  F_NONFINITE = GRPIC_FLAG_NONFINITE
 };
 
 struct PushArgs {
@@ -43,7 +44,7 @@ struct PushArgs {
 struct LocalStats {
   unsigned int herr_hist[kHistBins];
   unsigned int iter_hist[kHistBins];
-  unsigned int implicit_steps, noconv, removed, reflected, alive;
+  unsigned int implicit_steps, noconv, removed, reflected, alive, nonfinite;
 };
 
 __device__ __forceinline__ void stats_init(LocalStats& s) {
@@ -52,7 +53,7 @@ __device__ __forceinline__ void stats_init(LocalStats& s) {
     s.iter_hist[i] = 0;
   }
   if (threadIdx.x == 0)
-    s.implicit_steps = s.noconv = s.removed = s.reflected = s.alive = 0;
+    s.implicit_steps = s.noconv = s.removed = s.reflected = s.alive = s.nonfinite = 0;
 }
 
 __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
@@ -67,6 +68,7 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
     if (s.removed) atomicAdd(&g->removed, (unsigned long long)s.removed);
     if (s.reflected) atomicAdd(&g->reflected, (unsigned long long)s.reflected);
     if (s.alive) atomicAdd(&g->alive, (unsigned long long)s.alive);
+    if (s.nonfinite) atomicAdd(&g->nonfinite, (unsigned long long)s.nonfinite);
   }
 }
 
@@ -415,7 +417,14 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
                          double* out, double herr, int iters, uint8_t fl,
                          LocalStats& ls, double s0, double c0) {
   const ParticleView& P = A.p;
-  if (out[0] < A.r_min || out[0] > A.r_max) {
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) finite = finite && isfinite(out[i]);
+  if (!finite) {  // a state that is no number: taken out of the run
+    fl = F_REMOVED | F_NONFINITE;
+    atomicAdd(&ls.removed, 1u);
+    atomicAdd(&ls.nonfinite, 1u);
+  } else if (out[0] < A.r_min || out[0] > A.r_max) {
     fl = F_REMOVED;
     atomicAdd(&ls.removed, 1u);
   } else if (A.reflect) {

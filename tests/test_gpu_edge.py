@@ -205,3 +205,39 @@ def test_zero_dt_is_half_the_courant_limit():
     cfg = G.config_default(a=0.0, dt=0.0, max_particles=8)  # no grid: dt needed
     with pytest.raises(G.GrpicError):
         G.Context(cfg)
+
+
+def test_nonfinite_particle_is_removed_and_isolated():
+    """A particle whose step gives a non-finite state is flagged, counted and
+    removed; it deposits nothing, the fields stay finite, and every other
+    particle steps as the oracle says."""
+    cfg = _pic_cfg(n=2000)
+    g = oracle_grid(cfg)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 34, rplus(cfg.a), 18.0,
+                           cfg.theta0, np.pi - cfg.theta0, 0.1, w=2e-3)
+        P = ctx.get_particles()
+        z = P["z"].copy()
+        z[11, 3] = np.nan
+        z[500, 5] = np.inf
+        ctx.load_particles(z, P["qm"], P["w"], H0=P["H0"])
+        S0 = _levels(ctx)
+        P0 = ctx.get_particles()
+        ctx.step(1)
+        P1 = ctx.get_particles()
+        S1 = _levels(ctx)
+        d = ctx.diagnostics()
+    bad = np.zeros(len(z), bool)
+    bad[[11, 500]] = True
+    assert np.all(P1["flags"][bad] == G.FLAG_REMOVED | G.FLAG_NONFINITE)
+    assert d["nonfinite"] == 2
+    for lev in S1:
+        for c in range(len(S1[lev])):
+            assert np.all(np.isfinite(S1[lev][c]))
+    G6 = [S0[G.LEVEL_DH1][c].astype(np.float64) for c in range(3)] + \
+         [S1[G.LEVEL_BH][c].astype(np.float64) for c in range(3)]
+    keep = lambda D: {k: v[~bad] for k, v in D.items()}
+    err, _ = compare_push(cfg, keep(P0), keep(P1), push_params_from(cfg, O.FIELDS_GRID),
+                          grid=g, G6=G6)
+    assert err <= TOL_STATE

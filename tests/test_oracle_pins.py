@@ -447,6 +447,26 @@ def test_newton_solves_the_same_midpoint_equation(dt):
         assert np.mean(itp) > 2.5 * np.mean(itn)
 
 
+def test_nonfinite_state_is_removed_and_isolated():
+    """A particle whose step gives a non-finite state is flagged and taken
+    out (it then deposits nothing); the others step as without it."""
+    base = _c1_particles(16)
+    bad = base.copy()
+    bad.ur[5] = np.nan
+    bad.uph[9] = np.inf
+    for pusher, thr in ((O.RK4, 0.0), (O.HYB2, 1e-15), (O.HAM, 0.0)):
+        P = O.push_params(0.0, 0.05, pusher=pusher, thr=thr, r_min=2.0)
+        p1, p2 = base.copy(), bad.copy()
+        O.push(P, p1)
+        O.push(P, p2)
+        for k in (5, 9):
+            assert p2.flags[k] == O.REMOVED | O.NONFINITE
+        ok = np.ones(16, bool)
+        ok[[5, 9]] = False
+        assert np.array_equal(p1.state()[ok], p2.state()[ok])
+        assert np.array_equal(p1.flags[ok], p2.flags[ok])
+
+
 # --------------------------------------- own step lengths (Sec. 3.1.2, Table 2)
 def _clocked(p):
     p = p.copy()
