@@ -310,6 +310,38 @@ def table2_runs(G, W, t_end):
     return out
 
 
+def pusher_cost_ratios(G, W, n=1 << 20, dt=0.1, steps=100):
+    """The paper's only timing statement (Sec. 3.1, neutral orbits at
+    dt = 0.1): wall time of the implicit midpoint rule and of the
+    discrete-gradient scheme relative to RK4.  Here per particle-step on the
+    GPU, 2^20 particles of the test-particle distribution, each pusher
+    alone."""
+    out = {"particles": n, "dt": dt, "steps": steps}
+    for name, pusher in (("rk4", G.PUSH_RK4), ("imr", G.PUSH_IMR), ("ham", G.PUSH_HAM)):
+        cfg = G.config_default(a=W["a"], dt=dt, pusher=pusher, max_particles=n,
+                               r_remove_in=rplus(W["a"]))
+        with G.Context(cfg) as ctx:
+            ctx.init_particles(G.INIT_ORBITS, n, SEED + 1, 6.0, 20.0, np.pi / 4,
+                               3 * np.pi / 4, W["theta"])
+            ctx.step(5)
+            ctx.sync()
+            d0 = ctx.diagnostics()
+            t0 = time.perf_counter()
+            ctx.step(steps)
+            ctx.sync()
+            t = time.perf_counter() - t0
+            d1 = ctx.diagnostics()
+        it = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
+        impl = d1["implicit_steps"] - d0["implicit_steps"]
+        out[name] = {"particle_steps_per_s": d1["alive"] * steps / t, "ms_per_step": t * 1e3 / steps,
+                     "mean_iterations": float(it / impl) if impl else None}
+    out["imr_over_rk4"] = out["imr"]["ms_per_step"] / out["rk4"]["ms_per_step"]
+    out["ham_over_rk4"] = out["ham"]["ms_per_step"] / out["rk4"]["ms_per_step"]
+    print(f"[bench] pusher cost ratios: IMR/RK4 {out['imr_over_rk4']:.2f}, "
+          f"Ham/RK4 {out['ham_over_rk4']:.2f}", file=sys.stderr, flush=True)
+    return out
+
+
 def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
     """The charged test-particle workload (Kerr a=0.9, Wald field on 512^2,
     2^20 particles) with the implicit midpoint pusher on every particle,
@@ -568,9 +600,10 @@ def main():
                                       if v[1] > 0}
 
     ctx.close()
-    table2 = None
+    table2 = ratios = None
     if args.workload == "c1" and args.table2_t > 0:
         table2 = table2_runs(G, W, args.table2_t)
+        ratios = pusher_cost_ratios(G, W)
     learned = None
     if not args.no_learned:
         print("[bench] learned vs plain implicit guess", file=sys.stderr, flush=True)
@@ -605,6 +638,7 @@ def main():
         "learned_guess_training": mlp_info,
         "learned_guess": learned,
         "table2_a0": table2,
+        "pusher_cost_ratios": ratios,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -225,49 +225,70 @@ __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, dou
 // 2^-26 max(|m_j|, 1) (the step taken, (m_j + h) - m_j, divides), then
 // y -= J^{-1} G(y) by Gaussian elimination with partial pivoting; same
 // stopping test; Wq from the last midpoint evaluation
+// Every index into J is a compile-time constant (the column loop writes its
+// column through selects, the pivot swap is a chain of selects), so the
+// 6x7 system stays in registers.
 template <bool GRID>
 __device__ int imr_newton(const PushArgs& A, double dt, double qm, const double* z,
                           double s0, double c0, double* zk, double* Wq) {
   double p = 0.0;
   for (int k = 1; k <= A.kmax; ++k) {
-    double m[6], f0[6], J[6][7], sm, cm;
+    double m[6], f0[6], J[6][7] = {}, sm, cm;
 #pragma unroll
     for (int i = 0; i < 6; ++i) m[i] = 0.5 * (z[i] + zk[i]);
     sincos_near(m[1], z[1], s0, c0, &sm, &cm);
     eval<GRID>(A, qm, m, sm, cm, f0, &p);
 #pragma unroll 1
     for (int j = 0; j < 6; ++j) {
-      double mj[6], fj[6], pj, sj, cj;
+      double mj[6], fj[6], pj, sj, cj, mv = m[0];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) mj[i] = m[i];
-      double h = 0x1p-26 * fmax(fabs(m[j]), 1.0);
-      mj[j] = m[j] + h;
-      h = mj[j] - m[j];
+      for (int i = 1; i < 6; ++i) mv = i == j ? m[i] : mv;
+      double h = 0x1p-26 * fmax(fabs(mv), 1.0);
+      const double sv = mv + h;
+      h = sv - mv;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) mj[i] = i == j ? sv : m[i];
       sincos_near(mj[1], z[1], s0, c0, &sj, &cj);
       eval<GRID>(A, qm, mj, sj, cj, fj, &pj);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) J[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * dt * (fj[i] - f0[i]) / h;
+      for (int i = 0; i < 6; ++i) {
+        const double v = (i == j ? 1.0 : 0.0) - 0.5 * dt * (fj[i] - f0[i]) / h;
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) J[i][jj] = jj == j ? v : J[i][jj];
+      }
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) J[i][6] = -(zk[i] - z[i] - dt * f0[i]);
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
       int piv = c;
+      double best = fabs(J[c][c]);
+#pragma unroll
       for (int i = c + 1; i < 6; ++i)
-        if (fabs(J[i][c]) > fabs(J[piv][c])) piv = i;
-      if (piv != c)
-        for (int j = c; j < 7; ++j) {
-          double t = J[c][j];
-          J[c][j] = J[piv][j];
-          J[piv][j] = t;
+        if (fabs(J[i][c]) > best) {
+          piv = i;
+          best = fabs(J[i][c]);
         }
+#pragma unroll
+      for (int i = c + 1; i < 6; ++i)
+#pragma unroll
+        for (int j = c; j < 7; ++j) {
+          const double t = J[c][j];
+          J[c][j] = piv == i ? J[i][j] : t;
+          J[i][j] = piv == i ? t : J[i][j];
+        }
+#pragma unroll
       for (int i = c + 1; i < 6; ++i) {
         double l = J[i][c] / J[c][c];
+#pragma unroll
         for (int j = c; j < 7; ++j) J[i][j] -= l * J[c][j];
       }
     }
     double dy[6], zn[6];
+#pragma unroll
     for (int i = 5; i >= 0; --i) {
       double v = J[i][6];
+#pragma unroll
       for (int j = i + 1; j < 6; ++j) v -= J[i][j] * dy[j];
       dy[i] = v / J[i][i];
     }
@@ -292,9 +313,12 @@ __device__ int imr_newton(const PushArgs& A, double dt, double qm, const double*
 // Position quotients of the metric are cancellation-free divided
 // differences (metric_dd); below |dx| = eps the analytic derivative at the
 // midpoint replaces them.
-__constant__ int8_t kDGOrder[6][6] = {{0, 3, 1, 4, 2, 5}, {1, 4, 2, 5, 0, 3},
-                                      {2, 5, 0, 3, 1, 4}, {5, 2, 4, 1, 3, 0},
-                                      {3, 0, 5, 2, 4, 1}, {4, 1, 3, 0, 5, 2}};
+// The table is a compile-time constant and both loops below unroll fully, so
+// every step's variable and mask are literals: the four metric copies stay
+// in registers instead of being indexed through scratch memory.
+constexpr int8_t kDGOrder[6][6] = {{0, 3, 1, 4, 2, 5}, {1, 4, 2, 5, 0, 3},
+                                    {2, 5, 0, 3, 1, 4}, {5, 2, 4, 1, 3, 0},
+                                    {3, 0, 5, 2, 4, 1}, {4, 1, 3, 0, 5, 2}};
 
 __device__ __forceinline__ double lorentz(const Met& m, double ur, double ut,
                                           double up) {
@@ -310,8 +334,10 @@ __device__ int ham_dg(const PushArgs& A, double dt, const double* z, double* zk)
     metric(A.a, z[0], zk[1], M[2]);
     metric(A.a, zk[0], zk[1], M[3]);
     double grad[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
     for (int o = 0; o < 6; ++o) {
       int mask = 0;  // bit v set: variable v already at level n+1
+#pragma unroll
       for (int s = 0; s < 6; ++s) {
         int v = kDGOrder[o][s];
         double ur = (mask & 8) ? zk[3] : z[3];
