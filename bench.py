@@ -444,6 +444,8 @@ def main():
                     help="pair injection (Sec. 3.3: r+ <= r <= 6, multiplicity 3, density "
                          "5 n_GJ, Theta 0.5) after every N-th step (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the measured FP64-FMA and copy ceilings")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true",
@@ -599,6 +601,17 @@ def main():
         roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
                                       if v[1] > 0}
 
+    peaks = None
+    if not args.no_probe:
+        # the achievable ceilings of this device, next to the published peaks
+        peaks = ctx.probe_peaks()
+        print(f"[bench] measured ceilings: FP64 FMA {peaks['fp64_fma_tflops']:.1f} TFLOP/s, "
+              f"copy {peaks['copy_tbs']:.2f} TB/s", file=sys.stderr, flush=True)
+        if roof is not None:
+            for gd in [roof] + list(roof["groups"].values()):
+                ceil = (peaks["fp64_fma_tflops"] if gd["bound"] == "alu"
+                        else peaks["copy_tbs"] * 1e3)
+                gd["frac_of_measured"] = gd["achieved"] / ceil
     ctx.close()
     table2 = ratios = None
     if args.workload == "c1" and args.table2_t > 0:
@@ -634,6 +647,7 @@ def main():
         "h_error": herr_percentiles(d1["herr_hist"]),
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
         "roofline": roof,
+        "measured_peaks": peaks,
         "autotune": tune,
         "learned_guess_training": mlp_info,
         "learned_guess": learned,

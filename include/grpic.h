@@ -401,6 +401,17 @@ typedef struct grpic_tune_result {
 } grpic_tune_result;
 int grpic_autotune(grpic_ctx *ctx, int trial_steps, grpic_tune_result *out);
 
+/* ---- measured ceilings (measurement aid, not part of the method) --------
+ * Times, on the context's device and stream, (i) a kernel of independent
+ * FP64 fused multiply-adds on 8 waves per SIMD of every compute unit, no
+ * memory traffic, giving the achievable FP64 vector rate in TFLOP/s (an FMA
+ * counts 2 FLOP), and (ii) a 16-byte-per-thread copy between two 1 GiB
+ * buffers (read + write counted), giving the streaming HBM rate in TB/s.
+ * Each is the mean of 10 launches after 2 warm-up launches.  Allocates and
+ * frees 2 GiB of device memory (GRPIC_E_OOM if that fails); synchronises
+ * the stream.  GRPIC_E_INVALID on a null pointer.                          */
+int grpic_probe_peaks(grpic_ctx *ctx, double *fp64_fma_tflops, double *copy_tbs);
+
 /* ---- learned implicit guess (project extension, not in the paper) -----
  * A 14 -> 64 -> 64 -> 6 GELU network gives the implicit pusher's first
  * iterate as  base + scale (.) net((x - mean) * inv_std),  where base is the

@@ -339,6 +339,13 @@ class Context:
         self.cfg.push_waves_per_simd = r.push_waves_per_simd
         return {f[0]: getattr(r, f[0]) for f in TuneResult._fields_}
 
+    def probe_peaks(self):
+        """Measured FP64 FMA rate (TFLOP/s) and streaming copy rate (TB/s) of
+        the context's device."""
+        f, b = C.c_double(), C.c_double()
+        self._c("grpic_probe_peaks", C.byref(f), C.byref(b))
+        return {"fp64_fma_tflops": f.value, "copy_tbs": b.value}
+
     def mlp_get(self):
         theta = np.zeros(MLP_NPARAM, np.float32)
         mean, inv_std, scale = np.zeros(14, np.float32), np.zeros(14, np.float32), np.zeros(6, np.float32)

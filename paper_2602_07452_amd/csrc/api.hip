@@ -1292,6 +1292,15 @@ int grpic_autotune(grpic_ctx* c, int trial_steps, grpic_tune_result* out) {
   });
 }
 
+int grpic_probe_peaks(grpic_ctx* c, double* fp64_fma_tflops, double* copy_tbs) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (!fp64_fma_tflops || !copy_tbs) throw Error(GRPIC_E_INVALID, "null pointer");
+    GRPIC_HIP(hipStreamSynchronize(c->stream));
+    probe_peaks(c, fp64_fma_tflops, copy_tbs);
+  });
+}
+
 // ------------------------------------------------------ state snapshots
 namespace {
 

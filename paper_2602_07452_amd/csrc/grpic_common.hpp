@@ -191,6 +191,8 @@ void launch_energy_H0(grpic_ctx* c);
 void launch_clean(grpic_ctx* c, int iters);  // Sec. 2.4, both D chains
 constexpr int kInjMjK = 4096;                 // intervals of the MJ table
 long launch_inject(grpic_ctx* c, const double* mj, int mj_k, double mj_h);
+// measured FP64 FMA rate (TFLOP/s) and streaming copy rate (TB/s)
+void probe_peaks(grpic_ctx* c, double* fma_tflops, double* copy_tbs);
 void launch_sort(grpic_ctx* c);
 void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
