@@ -337,6 +337,9 @@ void free_all(grpic_ctx* c) {
   dfree(c->acc.Ft);
   dfree(c->tile_count);
   dfree(c->tile_offset);
+  dfree(c->dep_plan);
+  dfree(c->dep_plan_off);
+  dfree(c->dep_plan_meta);
   dfree(c->stats);
   mlp_free(c);
 }
@@ -346,6 +349,7 @@ void drop_graphs(grpic_ctx* c);
 // device state after particles change: sort, weights, initial rho
 void particles_loaded(grpic_ctx* c) {
   drop_graphs(c);
+  invalidate_deposit_plan(c);  // a new particle order
   launch_fill(c, c->stats, sizeof(Stats));
   c->steps = 0;
   if (c->pv.t && c->n > 0) launch_fill(c, c->pv.t, sizeof(double) * (size_t)c->n);
@@ -1419,6 +1423,7 @@ int grpic_set_state(grpic_ctx* c, const void* host, size_t bytes) {
     }
     c->n = (long)h.n;
     c->steps = (long)h.steps;
+    invalidate_deposit_plan(c);  // the snapshot's particle order
     c->qw_max = h.qw_max;
     c->has_neutral = h.has_neutral != 0;
     if (c->cfg.field_mode == GRPIC_FIELDS_EVOLVE)

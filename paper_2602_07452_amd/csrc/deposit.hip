@@ -26,7 +26,32 @@ struct DepArgs {
   unsigned* fallback;  // blocks that used global atomics (diagnostic)
   int* xqueue;         // particles whose move crosses a node-cell boundary
   unsigned* xcount;
+  const int* plan;       // chunk starts of the last sort (see chunk_range)
+  const int* plan_meta;  // {chunks, particles at the sort, valid}; null: no plan
 };
+
+// Particle range [beg, end) of deposit chunk b (false: past the last
+// chunk; a chunk may be empty).  With a valid plan the first chunks are its
+// runs of tiles whose node box fits the LDS bins (the dead particles the
+// sort put last need no deposit) and the rest are the particles appended
+// since, kDepChunk at a time; without one, equal chunks of the whole array.
+// Blocks stride over the chunks, so any grid size covers them all.
+__device__ __forceinline__ bool chunk_range(const DepArgs& A, long b, long& beg, long& end) {
+  long first = 0;
+  if (A.plan_meta && A.plan_meta[2]) {
+    const long total = A.plan_meta[0];
+    if (b < total) {
+      beg = A.plan[b];
+      end = min((long)A.plan[b + 1], A.p.n);
+      return true;
+    }
+    b -= total;
+    first = A.plan_meta[1];
+  }
+  beg = first + b * kDepChunk;
+  end = min(beg + (long)kDepChunk, A.p.n);
+  return beg < A.p.n;
+}
 
 // node cell c = q nr + p -> (p, q); (c + 1/2) / nr in FP64 is exact enough to
 // floor correctly for any grid that fits in memory
@@ -87,40 +112,60 @@ __device__ __forceinline__ void cell_flux(const Sink& S, double s, int p, int q,
   sink_add(S, 3, p + 1, q, qw * Ft1, s);
 }
 
-// what the deposit reads of one particle, loaded in one burst so that the
-// next particle's loads are in flight while this one is accumulated
+// what the deposit reads of one particle: raw loads only, so that nothing
+// waits for them until the record is used (the loads of the next records
+// stay in flight meanwhile)
 struct PRec {
+  double W1, W2, W3, N1, N2, N3, dphi, w;
+  int c0, c1;
+  uint8_t fl;
+  int8_t qm;
+};
+
+// k must be a valid particle index (callers clamp it)
+__device__ __forceinline__ void load_rec(const ParticleView& P, long k, PRec& d) {
+  d.fl = P.flags[k];
+  d.qm = P.qm[k];
+  d.w = P.w[k];
+  d.c0 = P.cell[k];
+  d.c1 = P.celln[k];
+  d.W1 = P.W[1][k];
+  d.W2 = P.W[2][k];
+  d.W3 = P.W[3][k];
+  d.N1 = P.Wn[1][k];
+  d.N2 = P.Wn[2][k];
+  d.N3 = P.Wn[3][k];
+  d.dphi = P.dphi[k];
+}
+
+// the deposit's view of a record
+struct PDep {
   double Wo[4], Wn[4], dphi, qw;
   int c0, c1;
   bool act;
 };
 
-__device__ __forceinline__ void load_rec(const ParticleView& P, long k, long end,
-                                         PRec& d) {
-  d.act = false;
-  if (k >= end) return;
-  uint8_t fl = P.flags[k];
-  int8_t qm = P.qm[k];
-  double w = P.w[k];
-  d.c0 = P.cell[k];
-  d.c1 = P.celln[k];
-#pragma unroll
-  for (int c = 1; c < 4; ++c) {
-    d.Wo[c] = P.W[c][k];
-    d.Wn[c] = P.Wn[c][k];
-  }
+__device__ __forceinline__ void unpack_rec(const PRec& r, PDep& d) {
+  d.Wo[1] = r.W1;
+  d.Wo[2] = r.W2;
+  d.Wo[3] = r.W3;
+  d.Wn[1] = r.N1;
+  d.Wn[2] = r.N2;
+  d.Wn[3] = r.N3;
   d.Wo[0] = 1.0 - d.Wo[1] - d.Wo[2] - d.Wo[3];
   d.Wn[0] = 1.0 - d.Wn[1] - d.Wn[2] - d.Wn[3];
-  d.dphi = P.dphi[k];
-  d.qw = (double)qm * w;
-  d.act = (fl & GRPIC_FLAG_ALIVE) && d.qw != 0.0;
+  d.dphi = r.dphi;
+  d.c0 = r.c0;
+  d.c1 = r.c1;
+  d.qw = (double)r.qm * r.w;
+  d.act = (r.fl & GRPIC_FLAG_ALIVE) && d.qw != 0.0;
 }
 
 // charge and J^phi of a particle, and its face fluxes when the move stays in
 // one node cell (returns false for a crossing move: fluxes left to
 // deposit_crossing)
 template <class Sink>
-__device__ bool deposit_particle(const DepArgs& A, const Sink& S, const PRec& d) {
+__device__ bool deposit_particle(const DepArgs& A, const Sink& S, const PDep& d) {
   const double s = A.acc.scale;
   const double qw = d.qw;
   int p0, q0, p1, q1;
@@ -207,7 +252,6 @@ __device__ void deposit_crossing(const DepArgs& A, const Sink& S, long k,
 }
 
 constexpr int kDepBlock = 512;
-constexpr int kDepChunk = 8192;   // particles per block
 constexpr int kDepSub = 2048;     // segment length when the chunk box is too big
 constexpr int kDepBins = 2048;    // LDS nodes per array (4 arrays x 16 KB)
 
@@ -225,20 +269,32 @@ __device__ __forceinline__ void segment_box(const DepArgs& A, long beg, long end
   }
   __syncthreads();
   int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
-  // unconditional loads, four particles at a time, so that they overlap
-#pragma unroll 4
-  for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
-    const uint8_t fl = P.flags[k];
-    const int8_t qm = P.qm[k];
-    const int c0 = P.cell[k], c1 = P.celln[k];
-    if (!(fl & GRPIC_FLAG_ALIVE) || qm == 0) continue;
-    int p0, q0, p1, q1;
-    split_cell(A, c0, p0, q0);
-    split_cell(A, c1, p1, q1);
-    pmin = min(pmin, min(p0, p1));
-    pmax = max(pmax, max(p0, p1));
-    qmin = min(qmin, min(q0, q1));
-    qmax = max(qmax, max(q0, q1));
+  // four particles per round, loads at clamped indices issued together and
+  // used through selects (no branch for the compiler to sink them into)
+  const long last = end - 1;
+  for (long k0 = beg + threadIdx.x; k0 < end; k0 += 4 * kDepBlock) {
+    uint8_t fl[4];
+    int8_t qm[4];
+    int c0[4], c1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long k = min(k0 + u * kDepBlock, last);
+      fl[u] = P.flags[k];
+      qm[u] = P.qm[k];
+      c0[u] = P.cell[k];
+      c1[u] = P.celln[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = k0 + u * kDepBlock < end && (fl[u] & GRPIC_FLAG_ALIVE) && qm[u] != 0;
+      int p0, q0, p1, q1;
+      split_cell(A, c0[u], p0, q0);
+      split_cell(A, c1[u], p1, q1);
+      pmin = ok ? min(pmin, min(p0, p1)) : pmin;
+      pmax = ok ? max(pmax, max(p0, p1)) : pmax;
+      qmin = ok ? min(qmin, min(q0, q1)) : qmin;
+      qmax = ok ? max(qmax, max(q0, q1)) : qmax;
+    }
   }
   if (pmax >= 0) {
     atomicMin(&box[0], pmin);
@@ -270,32 +326,42 @@ __device__ __forceinline__ void flush_list(const DepArgs& A, WaveList& X) {
   X.n = 0;
 }
 
-__device__ __forceinline__ void deposit_range(const DepArgs& A, long beg,
-                                              long end, const LdsSink* L,
-                                              WaveList& X) {
-  const ParticleView& P = A.p;
-  GlobalSink Gs{&A.acc, A.nr};
+template <class Sink>
+__device__ __forceinline__ void deposit_one(const DepArgs& A, const Sink& S, WaveList& X,
+                                            const PRec& r, long k, long end) {
   const int lane = threadIdx.x & 63;
-  // two particles ahead are in flight while one is accumulated
-  PRec cur, nxt, nxt2;
-  load_rec(P, beg + threadIdx.x, end, cur);
-  load_rec(P, beg + kDepBlock + threadIdx.x, end, nxt);
-  for (long kb = beg; kb < end; kb += kDepBlock) {  // uniform trip count
-    const long k = kb + threadIdx.x;
-    load_rec(P, k + 2 * kDepBlock, end, nxt2);
-    bool cross = false;
-    if (cur.act) {
-      bool done = L ? deposit_particle(A, *L, cur) : deposit_particle(A, Gs, cur);
-      cross = !done;
-    }
-    unsigned long long m = __ballot(cross);
-    if (m) {
-      if (X.n + 64 > kXList) flush_list(A, X);
-      if (cross) X.e[X.n + __popcll(m & ((1ull << lane) - 1ull))] = (int)k;
-      X.n += __popcll(m);
-    }
-    cur = nxt;
-    nxt = nxt2;
+  bool cross = false;
+  if (k < end) {
+    PDep d;
+    unpack_rec(r, d);
+    if (d.act) cross = !deposit_particle(A, S, d);
+  }
+  unsigned long long m = __ballot(cross);
+  if (m) {
+    if (X.n + 64 > kXList) flush_list(A, X);
+    if (cross) X.e[X.n + __popcll(m & ((1ull << lane) - 1ull))] = (int)k;
+    X.n += __popcll(m);
+  }
+}
+
+// Three records rotate (no register copies, which would wait for their
+// loads): while one is accumulated the next two are in flight.  Loads use
+// clamped indices; slots past the end are skipped.
+template <class Sink>
+__device__ __forceinline__ void deposit_range(const DepArgs& A, long beg, long end,
+                                              const Sink& S, WaveList& X) {
+  const ParticleView& P = A.p;
+  const long last = end - 1, t = threadIdx.x, B = kDepBlock;
+  PRec a, b, c;
+  load_rec(P, min(beg + t, last), a);
+  load_rec(P, min(beg + B + t, last), b);
+  for (long kb = beg; kb < end; kb += 3 * B) {  // uniform trip count
+    load_rec(P, min(kb + 2 * B + t, last), c);
+    deposit_one(A, S, X, a, kb + t, end);
+    load_rec(P, min(kb + 3 * B + t, last), a);
+    deposit_one(A, S, X, b, kb + B + t, end);
+    load_rec(P, min(kb + 4 * B + t, last), b);
+    deposit_one(A, S, X, c, kb + 2 * B + t, end);
   }
 }
 
@@ -319,9 +385,9 @@ __global__ __launch_bounds__(256) void k_deposit_crossing(DepArgs A) {
 
 __global__ void k_reset_xcount(unsigned* x) { *x = 0u; }
 
-// One block deposits a contiguous chunk of (tile-sorted) particles: the node
-// box covering every old and new cell of the chunk is accumulated in LDS and
-// flushed once.  A chunk whose box does not fit is redone in segments of
+// Per chunk of (tile-sorted) particles (chunk_range): the node box covering
+// every old and new cell of the chunk is accumulated in LDS and flushed
+// once.  A chunk whose box does not fit is redone in segments of
 // kDepSub particles with their own boxes; a segment that still does not fit
 // uses global atomics.
 __global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
@@ -329,45 +395,47 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
   __shared__ int box[4];
   __shared__ int xlist[(kDepBlock / 64) * kXList];
   WaveList X{xlist + (threadIdx.x >> 6) * kXList, 0};
-  const long beg = (long)blockIdx.x * kDepChunk;
-  const long end = min(beg + (long)kDepChunk, A.p.n);
-  for (int pass = 0; pass < 2; ++pass) {
-    const long seg = pass == 0 ? kDepChunk : kDepSub;
-    bool redo = false;
-    for (long sb = beg; sb < end; sb += seg) {
-      const long se = min(sb + seg, end);
-      segment_box(A, sb, se, box);
-      if (box[1] < 0) continue;  // nothing charged in this segment
-      const int bp0 = box[0], bq0 = box[2];
-      const int bw = box[1] - bp0 + 2, bh = box[3] - bq0 + 2;
-      const bool fits = bw * bh <= kDepBins;
-      if (!fits && pass == 0) {
-        redo = true;
-        break;
+  for (long b = blockIdx.x;; b += gridDim.x) {  // uniform over the block
+    long beg, end;
+    if (!chunk_range(A, b, beg, end)) break;
+    for (int pass = 0; pass < 2; ++pass) {
+      const long seg = pass == 0 ? kDepChunk : kDepSub;
+      bool redo = false;
+      for (long sb = beg; sb < end; sb += seg) {
+        const long se = min(sb + seg, end);
+        segment_box(A, sb, se, box);
+        if (box[1] < 0) continue;  // nothing charged in this segment
+        const int bp0 = box[0], bq0 = box[2];
+        const int bw = box[1] - bp0 + 2, bh = box[3] - bq0 + 2;
+        const bool fits = bw * bh <= kDepBins;
+        if (!fits && pass == 0) {
+          redo = true;
+          break;
+        }
+        if (!fits) {
+          if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
+          deposit_range(A, sb, se, GlobalSink{&A.acc, A.nr}, X);
+          continue;
+        }
+        LdsSink L{bins, bp0, bq0, bw, bw * bh};
+        for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
+        __syncthreads();
+        deposit_range(A, sb, se, L, X);
+        __syncthreads();
+        GlobalSink Gs{&A.acc, A.nr};
+        for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
+          long long v = bins[i];
+          if (v == 0) continue;
+          int a = i / L.n, r = i - a * L.n;
+          int jj = r / bw, ii = r - jj * bw;
+          // r-flux lives on cells (i < nr), theta-flux on rows j < nth
+          if ((a == 2 && bp0 + ii >= A.nr) || (a == 3 && bq0 + jj >= A.nth)) continue;
+          atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
+                    static_cast<unsigned long long>(v));
+        }
       }
-      if (!fits) {
-        if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
-        deposit_range(A, sb, se, nullptr, X);
-        continue;
-      }
-      LdsSink L{bins, bp0, bq0, bw, bw * bh};
-      for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
-      __syncthreads();
-      deposit_range(A, sb, se, &L, X);
-      __syncthreads();
-      GlobalSink Gs{&A.acc, A.nr};
-      for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
-        long long v = bins[i];
-        if (v == 0) continue;
-        int a = i / L.n, r = i - a * L.n;
-        int jj = r / bw, ii = r - jj * bw;
-        // r-flux lives on cells (i < nr), theta-flux on rows j < nth
-        if ((a == 2 && bp0 + ii >= A.nr) || (a == 3 && bq0 + jj >= A.nth)) continue;
-        atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
-                  static_cast<unsigned long long>(v));
-      }
+      if (!redo) break;
     }
-    if (!redo) break;
   }
   flush_list(A, X);
 }
@@ -468,7 +536,7 @@ __device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const do
   }
 }
 
-// one block per chunk of kDepChunk sorted particles: the chunk's node box
+// per chunk of sorted particles (chunk_range): the chunk's node box
 // (widened one node down, where the half-subgrid cells start) is summed in
 // LDS and flushed with one global atomic per touched entry; a chunk whose
 // box does not fit goes to global atomics directly
@@ -479,58 +547,61 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const do
   __shared__ long long bins[4 * kDepBins];
   __shared__ int box[4];
   const ParticleView& P = A.p;
-  const long beg = (long)blockIdx.x * kDepChunk;
-  const long end = min(beg + (long)kDepChunk, P.n);
-  if (threadIdx.x == 0) {
-    box[0] = 1 << 30;
-    box[1] = -1;
-    box[2] = 1 << 30;
-    box[3] = -1;
-  }
-  __syncthreads();
-  int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
-  for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
-    if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) continue;
-    int p, q;
-    split_cell(A, cell[k], p, q);
-    pmin = min(pmin, p);
-    pmax = max(pmax, p);
-    qmin = min(qmin, q);
-    qmax = max(qmax, q);
-  }
-  if (pmax >= 0) {
-    atomicMin(&box[0], pmin);
-    atomicMax(&box[1], pmax);
-    atomicMin(&box[2], qmin);
-    atomicMax(&box[3], qmax);
-  }
-  __syncthreads();
-  if (box[1] < 0) return;  // nothing charged in this chunk
-  const int bp0 = max(box[0] - 1, 0), bq0 = max(box[2] - 1, 0);
-  const int bw = box[1] + 2 - bp0, bh = box[3] + 2 - bq0;
-  if (bw * bh > kDepBins) {
-    if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
-    GlobalSink Gs{&A.acc, A.nr};
+  for (long b = blockIdx.x;; b += gridDim.x) {  // uniform over the block
+    long beg, end;
+    if (!chunk_range(A, b, beg, end)) break;
+    __syncthreads();  // the previous chunk is done with box and bins
+    if (threadIdx.x == 0) {
+      box[0] = 1 << 30;
+      box[1] = -1;
+      box[2] = 1 << 30;
+      box[3] = -1;
+    }
+    __syncthreads();
+    int pmin = 1 << 30, pmax = -1, qmin = 1 << 30, qmax = -1;
+    for (long k = beg + threadIdx.x; k < end; k += kDepBlock) {
+      if (!(P.flags[k] & GRPIC_FLAG_ALIVE) || P.qm[k] == 0) continue;
+      int p, q;
+      split_cell(A, cell[k], p, q);
+      pmin = min(pmin, p);
+      pmax = max(pmax, p);
+      qmin = min(qmin, q);
+      qmax = max(qmax, q);
+    }
+    if (pmax >= 0) {
+      atomicMin(&box[0], pmin);
+      atomicMax(&box[1], pmax);
+      atomicMin(&box[2], qmin);
+      atomicMax(&box[3], qmax);
+    }
+    __syncthreads();
+    if (box[1] < 0) continue;  // nothing charged in this chunk
+    const int bp0 = max(box[0] - 1, 0), bq0 = max(box[2] - 1, 0);
+    const int bw = box[1] + 2 - bp0, bh = box[3] + 2 - bq0;
+    if (bw * bh > kDepBins) {
+      if (threadIdx.x == 0) atomicAdd(A.fallback, 1u);
+      GlobalSink Gs{&A.acc, A.nr};
+      for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
+        if ((P.flags[k] & GRPIC_FLAG_ALIVE) && P.qm[k] != 0)
+          paper_particle(A, Gs, k, W1, W2, W3, cell, dt);
+      continue;
+    }
+    LdsSink L{bins, bp0, bq0, bw, bw * bh};
+    for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
+    __syncthreads();
     for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
       if ((P.flags[k] & GRPIC_FLAG_ALIVE) && P.qm[k] != 0)
-        paper_particle(A, Gs, k, W1, W2, W3, cell, dt);
-    return;
-  }
-  LdsSink L{bins, bp0, bq0, bw, bw * bh};
-  for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
-  __syncthreads();
-  for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
-    if ((P.flags[k] & GRPIC_FLAG_ALIVE) && P.qm[k] != 0)
-      paper_particle(A, L, k, W1, W2, W3, cell, dt);
-  __syncthreads();
-  GlobalSink Gs{&A.acc, A.nr};
-  for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
-    long long v = bins[i];
-    if (v == 0) continue;
-    int a = i / L.n, rr = i - a * L.n;
-    int jj = rr / bw, ii = rr - jj * bw;
-    atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
-              static_cast<unsigned long long>(v));
+        paper_particle(A, L, k, W1, W2, W3, cell, dt);
+    __syncthreads();
+    GlobalSink Gs{&A.acc, A.nr};
+    for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
+      long long v = bins[i];
+      if (v == 0) continue;
+      int a = i / L.n, rr = i - a * L.n;
+      int jj = rr / bw, ii = rr - jj * bw;
+      atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
+                static_cast<unsigned long long>(v));
+    }
   }
 }
 
@@ -544,7 +615,9 @@ static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int
   A.nth = c->nth;
   A.inv_nr = 1.0 / c->nr;
   A.fallback = &c->stats->deposit_fallback;
-  hipLaunchKernelGGL(k_deposit_paper, dim3(grid_for(c->n, kDepChunk)), dim3(kDepBlock), 0,
+  A.plan = c->dep_plan;
+  A.plan_meta = c->dep_plan_meta;
+  hipLaunchKernelGGL(k_deposit_paper, dim3(deposit_blocks(c)), dim3(kDepBlock), 0,
                      c->stream, A, W[1], W[2], W[3], cell, c->cfg.dt);
   GRPIC_HIP(hipGetLastError());
 }
@@ -629,8 +702,10 @@ void launch_deposit(grpic_ctx* c) {
     A.fallback = &c->stats->deposit_fallback;
     A.xqueue = c->xqueue;
     A.xcount = &c->stats->cross_count;
+    A.plan = c->dep_plan;
+    A.plan_meta = c->dep_plan_meta;
     hipLaunchKernelGGL(k_reset_xcount, dim3(1), dim3(1), 0, c->stream, A.xcount);
-    hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n, kDepChunk)), dim3(kDepBlock), 0,
+    hipLaunchKernelGGL(k_deposit, dim3(deposit_blocks(c)), dim3(kDepBlock), 0,
                        c->stream, A);
     unsigned xb = (unsigned)std::min<long>(grid_for(c->n, 256), 4L * c->num_cus);
     hipLaunchKernelGGL(k_deposit_crossing, dim3(xb), dim3(256), 0, c->stream, A);
@@ -654,6 +729,8 @@ void launch_deposit_initial(grpic_ctx* c) {
     A.nr = c->nr;
     A.nth = c->nth;
     A.inv_nr = 1.0 / c->nr;
+    A.plan = nullptr;
+    A.plan_meta = nullptr;
     if (c->cfg.deposit_mode == GRPIC_DEPOSIT_PAPER)
       launch_deposit_paper(c, P.W, P.cell);  // rho and J at the loaded state
     else

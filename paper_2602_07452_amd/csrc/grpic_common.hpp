@@ -123,6 +123,13 @@ struct grpic_ctx {
   int* tile_count = nullptr;
   int* tile_offset = nullptr;
   int ntiles = 0;
+  // deposit chunk plan of the last sort: chunk starts, their prefix by tile
+  // group, and {chunks, particles at the sort, valid}
+  int* dep_plan = nullptr;
+  int* dep_plan_off = nullptr;
+  int* dep_plan_meta = nullptr;
+  long dep_plan_cap = 0;  // entries of dep_plan
+  int plan_groups = 0;    // tile groups of the current plan layout
   double qw_max = 0;
   long steps = 0;
   // divergence cleaning (allocated on first use): coefficients
@@ -191,6 +198,10 @@ void launch_energy_H0(grpic_ctx* c);
 void launch_clean(grpic_ctx* c, int iters);  // Sec. 2.4, both D chains
 constexpr int kInjMjK = 4096;                 // intervals of the MJ table
 long launch_inject(grpic_ctx* c, const double* mj, int mj_k, double mj_h);
+constexpr int kDepChunk = 8192;  // particles per deposit block at most
+// deposit blocks to launch for the current particle count and plan layout
+long deposit_blocks(const grpic_ctx* c);
+void invalidate_deposit_plan(grpic_ctx* c);
 // measured FP64 FMA rate (TFLOP/s) and streaming copy rate (TB/s)
 void probe_peaks(grpic_ctx* c, double* fma_tflops, double* copy_tbs);
 void launch_sort(grpic_ctx* c);

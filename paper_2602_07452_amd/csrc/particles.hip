@@ -8,6 +8,8 @@
 // by default, tiles in serpentine order), dead particles last; keeps a
 // block's particles in a few neighbouring cells for the gather and the
 // deposit.
+#include <algorithm>
+
 #include "deposit_device.hpp"
 #include "sampling_device.hpp"
 
@@ -232,6 +234,92 @@ void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl) {
   GRPIC_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------- deposit chunk plan
+// After a sort the deposit takes its particles by runs of consecutive tiles:
+// groups of tiles covering about kPlanCells cells (their node box, plus the
+// drift until the next sort, fits the deposit's LDS bins), each group cut
+// every kDepChunk particles.  Near the inner boundary, where the
+// log-spaced cells are small and hold few particles, a chunk of kDepChunk
+// particles in sort order would span hundreds of tiles and miss the LDS
+// bins; there the groups become small chunks of their own.
+constexpr int kPlanCells = 512;
+
+int plan_group_tiles(const grpic_ctx* c) {
+  return std::max(1, kPlanCells / (c->cfg.tile_r * c->cfg.tile_th));
+}
+
+// chunks of each group (tile_end: end offsets of the tiles after the
+// scatter); nch[ngroups] = 0 closes the scan
+__global__ __launch_bounds__(256) void k_plan_count(const int* tile_end, int ntiles, int K,
+                                                    int ngroups, int* nch) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > ngroups) return;
+  if (g == ngroups) {
+    nch[g] = 0;
+    return;
+  }
+  const int t0 = g * K, t1 = min(t0 + K, ntiles);
+  const int s = t0 == 0 ? 0 : tile_end[t0 - 1], e = tile_end[t1 - 1];
+  nch[g] = (e - s + kDepChunk - 1) / kDepChunk;
+}
+
+// chunk starts from the groups' chunk offsets; start[total] = end of the
+// particles alive at the sort; meta = {total, n, 1}
+__global__ __launch_bounds__(256) void k_plan_write(const int* tile_end, int ntiles, int K,
+                                                    int ngroups, const int* off, int n,
+                                                    int* start, int* meta) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > ngroups) return;
+  if (g == ngroups) {
+    const int total = off[ngroups];
+    start[total] = tile_end[ntiles - 1];
+    meta[0] = total;
+    meta[1] = n;
+    meta[2] = 1;
+    return;
+  }
+  const int t0 = g * K;
+  const int s = t0 == 0 ? 0 : tile_end[t0 - 1];
+  for (int i = off[g]; i < off[g + 1]; ++i) start[i] = s + (i - off[g]) * kDepChunk;
+}
+
+void plan_deposit_chunks(grpic_ctx* c) {
+  const int K = plan_group_tiles(c);
+  const int ngroups = (c->ntiles + K - 1) / K;
+  const long need = ngroups + (c->cap + kDepChunk - 1) / kDepChunk + 2;
+  if (need > c->dep_plan_cap || !c->dep_plan_meta) {
+    dfree(c->dep_plan);
+    dfree(c->dep_plan_off);
+    if (!c->dep_plan_meta) c->dep_plan_meta = dalloc<int>(3);
+    c->dep_plan_cap = 0;
+    c->dep_plan = dalloc<int>(need);
+    c->dep_plan_off = dalloc<int>(need);
+    c->dep_plan_cap = need;
+  }
+  c->plan_groups = ngroups;
+  // tile_count is all zero between sorts; it holds the per-group counts
+  // here and the scan leaves it zero again
+  const unsigned gb = (unsigned)((ngroups + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_plan_count, dim3(gb), dim3(256), 0, c->stream, c->tile_offset,
+                     c->ntiles, K, ngroups, c->tile_count);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, c->stream, c->tile_count,
+                     c->dep_plan_off, ngroups + 1);
+  hipLaunchKernelGGL(k_plan_write, dim3(gb), dim3(256), 0, c->stream, c->tile_offset,
+                     c->ntiles, K, ngroups, c->dep_plan_off, (int)c->n, c->dep_plan,
+                     c->dep_plan_meta);
+  GRPIC_HIP(hipGetLastError());
+}
+
+long deposit_blocks(const grpic_ctx* c) {
+  // plan chunks <= groups + ceil(n_sort / kDepChunk); appended particles
+  // need ceil((n - n_sort) / kDepChunk) more
+  return (long)c->plan_groups + (c->n + kDepChunk - 1) / kDepChunk + 1;
+}
+
+void invalidate_deposit_plan(grpic_ctx* c) {
+  if (c->dep_plan_meta) launch_fill(c, c->dep_plan_meta, 3 * sizeof(int));
+}
+
 void launch_sort(grpic_ctx* c) {
   if (c->n == 0 || c->nr == 0) return;
   hipEvent_t ev;
@@ -254,6 +342,7 @@ void launch_sort(grpic_ctx* c) {
                      c->tile_count, c->tile_offset, c->ntiles + 1);
   hipLaunchKernelGGL(k_tile_scatter, g, b, 2 * sh, c->stream, A);
   GRPIC_HIP(hipGetLastError());
+  plan_deposit_chunks(c);
   ParticleView& P = c->pv;
   ParticleView& Q = c->alt;
   c->sort_flip ^= 1;
