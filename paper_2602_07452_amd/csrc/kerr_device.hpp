@@ -276,45 +276,71 @@ __device__ __forceinline__ double lerp2(float2 r0, float2 r1, double fr, double 
 // cells come from the uniform-grid formula; the radial cells from an FP32
 // estimate checked against the node tables.  The field corners of the
 // estimated cells are loaded together with those node values (one memory
-// round trip) and reloaded only when the estimate was one cell off.
-__device__ __forceinline__ void gather(const GridView& g, const FieldView& F,
-                                       double r, double th, double isg,
-                                       double* D, double* B) {
+// round trip) and reloaded only when the estimate was one cell off.  Split
+// in two so that a caller can compute between issuing the loads
+// (gather_issue) and using them (gather_finish).
+struct GatherLoads {
+  float2 c[12];
+  double rn0, rn1, irn, rh0, rh1, irh;
+  int pn, ph, qn, qh;
+};
+
+__device__ __forceinline__ void gather_issue(const GridView& g, const FieldView& F,
+                                             double r, double th, GatherLoads& L) {
   const int nr = g.nr, nrn = nr + 1, nrh = nr;
   const double lt = (th - g.th0) * g.inv_dth;
-  const int qn = theta_cell<false>(g, th, lt, g.nth + 1);
-  const int qh = theta_cell<true>(g, th, lt, g.nth);
+  L.qn = theta_cell<false>(g, th, lt, g.nth + 1);
+  L.qh = theta_cell<true>(g, th, lt, g.nth);
   const float lr = radial_coord(g, r);
   int pn = (int)floorf(lr), ph = (int)floorf(lr - 0.5f);
-  pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
-  ph = ph < 0 ? 0 : (ph > nr - 2 ? nr - 2 : ph);
-  float2 c[12];
-  corner_loads(F, nrn, nrh, pn, ph, qn, qh, c);
-  double rn0 = g.rn[pn], rn1 = g.rn[pn + 1], irn = g.idrn[pn];
-  double rh0 = g.rh[ph], rh1 = g.rh[ph + 1], irh = g.idrh[ph];
-  int pn2 = pn, ph2 = ph;
-  if (pn > 0 && r < rn0) --pn2;
-  else if (pn < nr - 1 && r >= rn1) ++pn2;
-  if (ph > 0 && r < rh0) --ph2;
-  else if (ph < nr - 2 && r >= rh1) ++ph2;
+  L.pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
+  L.ph = ph < 0 ? 0 : (ph > nr - 2 ? nr - 2 : ph);
+  corner_loads(F, nrn, nrh, L.pn, L.ph, L.qn, L.qh, L.c);
+  L.rn0 = g.rn[L.pn];
+  L.rn1 = g.rn[L.pn + 1];
+  L.irn = g.idrn[L.pn];
+  L.rh0 = g.rh[L.ph];
+  L.rh1 = g.rh[L.ph + 1];
+  L.irh = g.idrh[L.ph];
+}
+
+__device__ __forceinline__ void gather_finish(const GridView& g, const FieldView& F,
+                                              double r, double th, double isg,
+                                              GatherLoads& L, double* D, double* B) {
+  const int nr = g.nr, nrn = nr + 1, nrh = nr;
+  int pn = L.pn, ph = L.ph, pn2 = pn, ph2 = ph;
+  if (pn > 0 && r < L.rn0) --pn2;
+  else if (pn < nr - 1 && r >= L.rn1) ++pn2;
+  if (ph > 0 && r < L.rh0) --ph2;
+  else if (ph < nr - 2 && r >= L.rh1) ++ph2;
+  double rn0 = L.rn0, irn = L.irn, rh0 = L.rh0, irh = L.irh;
   if (pn2 != pn || ph2 != ph) {
     pn = pn2;
     ph = ph2;
-    corner_loads(F, nrn, nrh, pn, ph, qn, qh, c);
+    corner_loads(F, nrn, nrh, pn, ph, L.qn, L.qh, L.c);
     rn0 = g.rn[pn];
     irn = g.idrn[pn];
     rh0 = g.rh[ph];
     irh = g.idrh[ph];
   }
+  const float2* c = L.c;
   const double frn = clamp01((r - rn0) * irn), frh = clamp01((r - rh0) * irh);
-  const double ftn = clamp01((th - theta_node(g, qn)) * g.inv_dth);
-  const double fth = clamp01((th - theta_half(g, qh)) * g.inv_dth);
+  const double ftn = clamp01((th - theta_node(g, L.qn)) * g.inv_dth);
+  const double fth = clamp01((th - theta_half(g, L.qh)) * g.inv_dth);
   D[0] = lerp2(c[0], c[1], frh, ftn) * isg;
   D[1] = lerp2(c[2], c[3], frn, fth) * isg;
   D[2] = lerp2(c[4], c[5], frn, ftn) * isg;
   B[0] = lerp2(c[6], c[7], frn, fth) * isg;
   B[1] = lerp2(c[8], c[9], frh, ftn) * isg;
   B[2] = lerp2(c[10], c[11], frh, fth) * isg;
+}
+
+__device__ __forceinline__ void gather(const GridView& g, const FieldView& F,
+                                       double r, double th, double isg,
+                                       double* D, double* B) {
+  GatherLoads L;
+  gather_issue(g, F, r, th, L);
+  gather_finish(g, F, r, th, isg, L, D, B);
 }
 
 // ------------------------------------------------------- equations of motion

@@ -82,7 +82,10 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
 //   + d(s2)_k / P (a^2 u_r^2 - u_ph^2 / s2^2) - d(xi)_k / xi^2 u_r^2,
 // evaluated in that factored form (fewer live values than the twelve
 // derivatives; equal to rounding).
-template <bool GRID>
+// SPLIT: issue the field loads first and compute the gravity terms while
+// they are in flight (more registers: pays where occupancy is already two
+// waves per SIMD, the implicit pass)
+template <bool GRID, bool SPLIT = false>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      const double* z, double s, double c, double* f,
                                      double* pw, double* e = nullptr) {
@@ -93,7 +96,14 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double ixi = rho2 * iS, alpha = fsqrt(ixi), betar = 2.0 * r * iS;
   const double sg = fabs(s) * fsqrt(rho2 * S);
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
-  if (GRID && qm != 0.0) gather(A.g, A.f, r, z[1], rcp(sg), D, B);
+  const bool charged = GRID && qm != 0.0;
+  GatherLoads gl;
+  if (charged) {
+    if constexpr (SPLIT)
+      gather_issue(A.g, A.f, r, z[1], gl);
+    else
+      gather(A.g, A.f, r, z[1], rcp(sg), D, B);
+  }
   // contravariant momentum gamma^ij u_j and the Lorentz factor
   const double irp = a * irho2;
   const double Ur = (a2 * s2 * irho2 + ixi) * ur + irp * up;
@@ -114,6 +124,9 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double dxt = 4.0 * r * a2 * sc * i4;                      // d_theta xi
   const double gr = dxr * Cq + aiG * r * i4 * Aq;
   const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
+  if constexpr (SPLIT) {
+    if (charged) gather_finish(A.g, A.f, r, z[1], rcp(sg), gl, D, B);
+  }
   if (qm != 0.0) {
     // Lorentz force: alpha (q/m) [gamma_ij D^j + sqrt(g) eta_ijk U^j B^k / Gamma]
     const double xi = S * irho2;
@@ -195,7 +208,7 @@ __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
 }
 
 // implicit midpoint rule by fixed-point iteration; zk: guess in, result out
-template <bool GRID>
+template <bool GRID, bool SPLIT = false>
 __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, double s0,
                    double c0, double* zk, double* Wq) {
   double p = 0.0;
@@ -204,7 +217,7 @@ __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, dou
 #pragma unroll
     for (int i = 0; i < 6; ++i) zm[i] = 0.5 * (z[i] + zk[i]);
     sincos_near(zm[1], z[1], s0, c0, &sm, &cm);
-    eval<GRID>(A, qm, zm, sm, cm, f, &p);
+    eval<GRID, SPLIT>(A, qm, zm, sm, cm, f, &p);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zn[i] = z[i] + dt * f[i];
     bool c = small_change(zn, zk, A.tol);
@@ -651,7 +664,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       if constexpr (NEWTON)
         it = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
       else
-        it = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+        it = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq);
       if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
         // no convergence from the learned guess: restart from z^n
 #pragma unroll
@@ -660,7 +673,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         if constexpr (NEWTON)
           it2 = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
         else
-          it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
+          it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq);
         it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
       }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
