@@ -615,8 +615,10 @@ static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int
   A.nth = c->nth;
   A.inv_nr = 1.0 / c->nr;
   A.fallback = &c->stats->deposit_fallback;
-  A.plan = c->dep_plan;
-  A.plan_meta = c->dep_plan_meta;
+  // equal chunks: its per-particle work is large, so the few chunks whose
+  // box misses the LDS bins cost less than the plan's many small chunks
+  A.plan = nullptr;
+  A.plan_meta = nullptr;
   hipLaunchKernelGGL(k_deposit_paper, dim3(deposit_blocks(c)), dim3(kDepBlock), 0,
                      c->stream, A, W[1], W[2], W[3], cell, c->cfg.dt);
   GRPIC_HIP(hipGetLastError());

@@ -242,7 +242,7 @@ void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl) {
 // log-spaced cells are small and hold few particles, a chunk of kDepChunk
 // particles in sort order would span hundreds of tiles and miss the LDS
 // bins; there the groups become small chunks of their own.
-constexpr int kPlanCells = 512;
+constexpr int kPlanCells = 1024;
 
 int plan_group_tiles(const grpic_ctx* c) {
   return std::max(1, kPlanCells / (c->cfg.tile_r * c->cfg.tile_th));
