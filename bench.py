@@ -249,6 +249,29 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
             alive = alive0 & ((p.flags & 1) != 0)
             O.deposit(g, cfg.dt, old, p.state()[:, :3], p.qm * p.w, alive.astype(np.int32))
     t_part = (time.perf_counter() - t0) / (sample_steps * sample_particles)
+    # the same particle work on one thread (a sixteenth of the sample)
+    t_part1 = None
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        n1 = max(sample_particles // 16, 1024)
+        q = O.Particles(n1)
+        for k in ("r", "th", "ph", "ur", "uth", "uph", "qm", "w", "H0", "herr"):
+            getattr(q, k)[:] = getattr(p, k)[:n1]
+        q.flags[:] = p.flags[:n1]
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        for _ in range(sample_steps):
+            old = q.state()[:, :3].copy()
+            alive0 = (q.flags & 1) != 0
+            O.push(P, q, grid=g, G=G6)
+            if evolve:
+                alive = alive0 & ((q.flags & 1) != 0)
+                O.deposit(g, cfg.dt, old, q.state()[:, :3], q.qm * q.w, alive.astype(np.int32))
+        t_part1 = (time.perf_counter() - t0) / (sample_steps * n1)
+        gomp.omp_set_num_threads(nthreads)
+    except OSError:
+        pass
     t_grid = 0.0
     if evolve:
         F = O.Fields.uniform_levels(g, D, B)
@@ -257,7 +280,12 @@ def cpu_baseline(W, cfg, sample_particles, sample_steps):
         t_grid = time.perf_counter() - t1
     n_full = W["n"]
     rate = n_full / (t_grid + n_full * t_part)
+    extra = {}
+    if t_part1 is not None:
+        extra = {"value_1thread": n_full / (t_grid + n_full * t_part1),
+                 "t_particle_1thread_s": t_part1}
     return {"value": rate, "unit": "particle-steps/s", "cores": nthreads, "kind": "oracle",
+            **extra,
             "sample": (f"{sample_particles} particles x {sample_steps} steps of push"
                        + (" + deposit, plus one full grid step (Maxwell sub-steps) on the "
                           f"{cfg.nr}x{cfg.nth} grid; rate = N / (t_grid + N t_particle) for "
