@@ -191,41 +191,72 @@ __device__ bool deposit_particle(const DepArgs& A, const Sink& S, const PDep& d)
   return false;
 }
 
-// face fluxes of a move that crosses node-cell boundaries: the straight move
-// is walked cell by cell
-template <class Sink>
-__device__ void deposit_crossing(const DepArgs& A, const Sink& S, long k,
-                                 double qw, int p0, int q0, int p1, int q1) {
+// what the walk of a crossing move reads of its particle
+struct XRec {
+  double Wo[4], Wn[4], r0, t0, r1, t1, qw;
+  int p0, q0, p1, q1;
+};
+
+// k must be a valid particle index (callers clamp it)
+__device__ __forceinline__ void load_xrec(const DepArgs& A, long k, XRec& x) {
   const ParticleView& P = A.p;
+#pragma unroll
+  for (int c = 1; c < 4; ++c) {
+    x.Wo[c] = P.W[c][k];
+    x.Wn[c] = P.Wn[c][k];
+  }
+  x.r0 = P.r_old[k];
+  x.t0 = P.th_old[k];
+  x.r1 = P.r[k];
+  x.t1 = P.th[k];
+  x.qw = (double)P.qm[k] * P.w[k];
+  split_cell(A, P.cell[k], x.p0, x.q0);
+  split_cell(A, P.celln[k], x.p1, x.q1);
+}
+
+// face fluxes of a move that crosses node-cell boundaries: the straight move
+// is walked cell by cell.  Each step loads the node values it may need in
+// one burst (radii of the cell and of both radial neighbours, sin and cos
+// of the cell's lower angle and of the angular neighbour toward the end
+// cell) and evaluates sin, cos of the crossing point once for both cells.
+template <class Sink>
+__device__ void deposit_crossing(const DepArgs& A, const Sink& S, const XRec& x) {
+  const GridView& g = A.g;
   double Wo[4], Wn[4];
 #pragma unroll
   for (int c = 1; c < 4; ++c) {
-    Wo[c] = P.W[c][k];
-    Wn[c] = P.Wn[c][k];
+    Wo[c] = x.Wo[c];
+    Wn[c] = x.Wn[c];
   }
   Wo[0] = 1.0 - Wo[1] - Wo[2] - Wo[3];
   Wn[0] = 1.0 - Wn[1] - Wn[2] - Wn[3];
-  const double s = A.acc.scale;
-  const double r0 = P.r_old[k], t0 = P.th_old[k], r1 = P.r[k], t1 = P.th[k];
-  int cp = p0, cq = q0;
+  const double s = A.acc.scale, qw = x.qw;
+  const double r0 = x.r0, t0 = x.t0, r1 = x.r1, t1 = x.t1;
+  const int p1 = x.p1, q1 = x.q1;
+  int cp = x.p0, cq = x.q0;
   double Wa[4] = {Wo[0], Wo[1], Wo[2], Wo[3]};
   for (int guard = 0; guard < 16 && (cp != p1 || cq != q1); ++guard) {
-    double tr = 2.0, tt = 2.0;
     int br = -1, bt = -1;
     if (p1 > cp) br = cp + 1;
     else if (p1 < cp) br = cp;
     if (q1 > cq) bt = cq + 1;
     else if (q1 < cq) bt = cq;
-    if (br >= 0) tr = (A.g.rn[br] - r0) / (r1 - r0);
-    if (bt >= 0) tt = (A.g.tn[bt] - t0) / (t1 - t0);
-    double xr, xt, Wb[4], Wc[4];
+    const int qo = q1 > cq ? cq + 1 : (cq > 0 ? cq - 1 : 0);
+    const double rm = g.rn[cp > 0 ? cp - 1 : 0], ra = g.rn[cp], rb = g.rn[cp + 1],
+                 rc = g.rn[cp + 2 <= A.nr ? cp + 2 : A.nr];
+    const double sq = g.stn[cq], cqs = g.ctn[cq], so = g.stn[qo], co = g.ctn[qo];
+    const double tb = g.tn[bt >= 0 ? bt : cq];
+    const double tr = br >= 0 ? ((br > cp ? rb : ra) - r0) / (r1 - r0) : 2.0;
+    const double tt = bt >= 0 ? (tb - t0) / (t1 - t0) : 2.0;
+    double Wb[4], Wc[4];
     if (tr <= tt) {
-      xr = A.g.rn[br];
-      xt = t0 + tr * (t1 - t0);
-      dep_weights(A.g, xr, xt, cp, cq, Wb);
+      const double xr = br > cp ? rb : ra, xt = t0 + tr * (t1 - t0);
+      double st, ct;
+      fsincos(xt, &st, &ct);
+      dep_weights_at(g, xr, xt, st, ct, ra, rb, sq, cqs, cq, Wb);
       cell_flux(S, s, cp, cq, Wa, Wb, qw);
-      int np = (br > cp) ? cp + 1 : cp - 1;
-      dep_weights(A.g, xr, xt, np, cq, Wc);
+      const int np = (br > cp) ? cp + 1 : cp - 1;
+      dep_weights_at(g, xr, xt, st, ct, np > cp ? rb : rm, np > cp ? rc : ra, sq, cqs, cq, Wc);
       // node (br, cq+1): slot 3 of the old cell if br = cp+1 else slot 2;
       // in the new cell slot 2 if br = np else slot 3
       double prev = (br == cp + 1) ? Wb[3] : Wb[2];
@@ -233,12 +264,13 @@ __device__ void deposit_crossing(const DepArgs& A, const Sink& S, long k,
       sink_add(S, 3, br, cq, qw * (now - prev), s);
       cp = np;
     } else {
-      xr = r0 + tt * (r1 - r0);
-      xt = A.g.tn[bt];
-      dep_weights(A.g, xr, xt, cp, cq, Wb);
+      const double xr = r0 + tt * (r1 - r0), xt = tb;
+      double st, ct;
+      fsincos(xt, &st, &ct);
+      dep_weights_at(g, xr, xt, st, ct, ra, rb, sq, cqs, cq, Wb);
       cell_flux(S, s, cp, cq, Wa, Wb, qw);
-      int nq = (bt > cq) ? cq + 1 : cq - 1;
-      dep_weights(A.g, xr, xt, cp, nq, Wc);
+      const int nq = (bt > cq) ? cq + 1 : cq - 1;  // = qo
+      dep_weights_at(g, xr, xt, st, ct, ra, rb, so, co, nq, Wc);
       // node (cp+1, bt): slot 3 of the old cell if bt = cq+1 else slot 1
       double prev = (bt == cq + 1) ? Wb[3] : Wb[1];
       double now = (bt == nq) ? Wc[1] : Wc[3];
@@ -366,20 +398,16 @@ __device__ __forceinline__ void deposit_range(const DepArgs& A, long beg, long e
 }
 
 // face fluxes of the queued crossing moves (grid-stride over the queue,
-// global atomics)
+// global atomics).  Loading the next move's record while one is walked was
+// measured slower (223 VGPRs, two waves per SIMD).
 __global__ __launch_bounds__(256) void k_deposit_crossing(DepArgs A) {
-  const ParticleView& P = A.p;
   GlobalSink Gs{&A.acc, A.nr};
   const unsigned nq = *A.xcount;
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < nq;
        i += gridDim.x * blockDim.x) {
-    long k = A.xqueue[i];
-    int c0 = P.cell[k], c1 = P.celln[k];
-    double qw = (double)P.qm[k] * P.w[k];
-    int p0, q0, p1, q1;
-    split_cell(A, c0, p0, q0);
-    split_cell(A, c1, p1, q1);
-    deposit_crossing(A, Gs, k, qw, p0, q0, p1, q1);
+    XRec x;
+    load_xrec(A, A.xqueue[i], x);
+    deposit_crossing(A, Gs, x);
   }
 }
 
