@@ -75,16 +75,20 @@ __device__ __forceinline__ void dep_weights_box(const GridView& g, double r, dou
     for (int i = 0; i < 7; ++i) {
       const double rr = i < 3 ? ra + i * h1r : (i == 3 ? r : r + (i - 3) * h2r);
       double rho2 = rr * rr + C2;
-      double f = fsqrt(rho2 * (rho2 + 2.0 * rr));
-      double wa_r = (i == 0 || i == 3) ? 0.5 : (i < 3 ? 1.0 : 0.0);
-      double wb_r = (i == 3 || i == 6) ? 0.5 : (i > 3 ? 1.0 : 0.0);
-      rowa += wa_r * f;
-      rowb += wb_r * f;
+      double f = fsqrt_lo(rho2 * (rho2 + 2.0 * rr));
+      // a sample outside a sub-rectangle has weight 0 there (its term would
+      // add +0 exactly): only the nonzero terms are formed
+      if (i <= 3) rowa += ((i == 0 || i == 3) ? 0.5 : 1.0) * f;
+      if (i >= 3) rowb += ((i == 3 || i == 6) ? 0.5 : 1.0) * f;
     }
-    Vaa += wa_t * Sabs * rowa;  // [ra, r] x [ta, th]
-    Vba += wa_t * Sabs * rowb;  // [r, rb] x [ta, th]
-    Vab += wb_t * Sabs * rowa;  // [ra, r] x [th, tb]
-    Vbb += wb_t * Sabs * rowb;  // [r, rb] x [th, tb]
+    if (j <= 3) {
+      Vaa += wa_t * Sabs * rowa;  // [ra, r] x [ta, th]
+      Vba += wa_t * Sabs * rowb;  // [r, rb] x [ta, th]
+    }
+    if (j >= 3) {
+      Vab += wb_t * Sabs * rowa;  // [ra, r] x [th, tb]
+      Vbb += wb_t * Sabs * rowb;  // [r, rb] x [th, tb]
+    }
     if (j < 2 || (j >= 3 && j < 6)) {
       const double ch = j < 3 ? ch1 : ch2, sh = j < 3 ? sh1 : sh2;
       const double Sn = Sj * ch + Cj * sh;

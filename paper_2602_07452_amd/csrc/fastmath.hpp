@@ -31,6 +31,16 @@ __device__ __forceinline__ double fsqrt(double x) {
   return fma(h, r, s);
 }
 
+// sqrt(x) to about 2^-48 relative (the Goldschmidt step of fsqrt without
+// its final correction), for the many samples of the deposit weights, whose
+// sums are rounded to FP32 in the end
+__device__ __forceinline__ double fsqrt_lo(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  double r = fma(-s, h, 0.5);
+  return fma(s, r, s);
+}
+
 // sin and cos of x for |x| < 100 (polar angles here lie near [0, pi]):
 // Cody-Waite reduction x = k pi/2 + t with pi/2 split in two parts, t in
 // [-pi/4, pi/4]; Taylor polynomials of degree 17 (sin) and 16 (cos), whose
