@@ -403,11 +403,14 @@ int grpic_autotune(grpic_ctx *ctx, int trial_steps, grpic_tune_result *out);
 
 /* ---- measured ceilings (measurement aid, not part of the method) --------
  * Times, on the context's device and stream, (i) a kernel of independent
- * FP64 fused multiply-adds on 8 waves per SIMD of every compute unit, no
- * memory traffic, giving the achievable FP64 vector rate in TFLOP/s (an FMA
- * counts 2 FLOP), and (ii) a 16-byte-per-thread copy between two 1 GiB
- * buffers (read + write counted), giving the streaming HBM rate in TB/s.
- * Each is the mean of 10 launches after 2 warm-up launches.  Allocates and
+ * FP64 fused multiply-adds on every compute unit, no memory traffic, giving
+ * the achievable FP64 vector rate in TFLOP/s (an FMA counts 2 FLOP; the
+ * best of 8 or 16 waves per SIMD and 8 or 16 chains per thread), and (ii) a
+ * grid-stride copy of 16-byte elements between two 1 GiB buffers (read +
+ * write counted), giving the streaming HBM rate in TB/s (the best of 4, 8
+ * or 16 blocks per compute unit, cached or nontemporal accesses, and the
+ * HIP runtime's device-to-device copy of the same buffers).  Each
+ * setting is the mean of 10 launches after 2 warm-up launches.  Allocates and
  * frees 2 GiB of device memory (GRPIC_E_OOM if that fails); synchronises
  * the stream.  GRPIC_E_INVALID on a null pointer.                          */
 int grpic_probe_peaks(grpic_ctx *ctx, double *fp64_fma_tflops, double *copy_tbs);

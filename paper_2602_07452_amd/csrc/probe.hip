@@ -2,46 +2,59 @@
 // the device the context runs on: the FP64 vector fused-multiply-add rate
 // (independent FMA chains, no memory traffic) and the streaming HBM rate (a
 // copy between two buffers far larger than the last-level cache).
+#include <algorithm>
+
 #include "grpic_common.hpp"
 
 namespace grpic {
 
 namespace {
 
-constexpr int kFmaChains = 8;
-
-// each thread runs kFmaChains independent chains a <- a m + c; the sums are
+// each thread runs CHAINS independent chains a <- a m + c; the sums are
 // stored so that the chains cannot be removed
+template <int CHAINS>
 __global__ __launch_bounds__(256) void k_probe_fma(double* out, int iters, double x0) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double a[kFmaChains];
+  double a[CHAINS];
 #pragma unroll
-  for (int j = 0; j < kFmaChains; ++j) a[j] = x0 + 1e-9 * (double)(t + j);
+  for (int j = 0; j < CHAINS; ++j) a[j] = x0 + 1e-9 * (double)(t + j);
   const double m = 0.9999999, c = 1e-7;
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int j = 0; j < kFmaChains; ++j) a[j] = fma(a[j], m, c);
+    for (int j = 0; j < CHAINS; ++j) a[j] = fma(a[j], m, c);
   }
   double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < kFmaChains; ++j) s += a[j];
+  for (int j = 0; j < CHAINS; ++j) s += a[j];
   out[t] = s;
 }
 
-// dst = src, grid-stride, four 16-byte loads in flight per thread
-__global__ __launch_bounds__(256) void k_probe_copy(const double2* __restrict__ src,
-                                                    double2* __restrict__ dst, long n) {
+// dst = src, grid-stride, four 16-byte loads in flight per thread; NT:
+// nontemporal loads and stores (no cache allocation)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__global__ __launch_bounds__(256) void k_probe_copy(const dvec2* __restrict__ src,
+                                                    dvec2* __restrict__ dst, long n) {
   const long stride = (long)gridDim.x * blockDim.x;
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  auto ld = [](const dvec2* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+  };
+  auto st = [](dvec2* p, dvec2 v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+  };
   for (; i + 3 * stride < n; i += 4 * stride) {
-    const double2 v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride],
-                  v3 = src[i + 3 * stride];
-    dst[i] = v0;
-    dst[i + stride] = v1;
-    dst[i + 2 * stride] = v2;
-    dst[i + 3 * stride] = v3;
+    const dvec2 v0 = ld(src + i), v1 = ld(src + i + stride), v2 = ld(src + i + 2 * stride),
+                v3 = ld(src + i + 3 * stride);
+    st(dst + i, v0);
+    st(dst + i + stride, v1);
+    st(dst + i + 2 * stride, v2);
+    st(dst + i + 3 * stride, v3);
   }
-  for (; i < n; i += stride) dst[i] = src[i];
+  for (; i < n; i += stride) st(dst + i, ld(src + i));
 }
 
 template <class Launch>
@@ -65,35 +78,60 @@ double mean_ms(hipStream_t s, int warm, int reps, Launch&& launch) {
 
 void probe_peaks(grpic_ctx* c, double* fma_tflops, double* copy_tbs) {
   const hipStream_t s = c->stream;
-  // FMA: 8 waves per SIMD on every compute unit
-  const unsigned blocks = (unsigned)c->num_cus * 8;
-  const long threads = (long)blocks * 256;
+  // FMA: 8 or 16 waves per SIMD on every compute unit, 8 or 16 chains per
+  // thread; the best of the four
   const int iters = 4096;
-  double* out = dalloc<double>(threads);
-  double ms = 0.0;
+  const long max_threads = (long)c->num_cus * 16 * 256;
+  double* out = dalloc<double>(max_threads);
+  double best = 0.0;
   try {
-    ms = mean_ms(s, 2, 10, [&] {
-      hipLaunchKernelGGL(k_probe_fma, dim3(blocks), dim3(256), 0, s, out, iters, 1.0);
-    });
-    GRPIC_HIP(hipGetLastError());
+    for (int wps : {8, 16}) {
+      const unsigned blocks = (unsigned)c->num_cus * wps;
+      const long threads = (long)blocks * 256;
+      for (int chains : {8, 16}) {
+        const double ms = mean_ms(s, 2, 10, [&] {
+          if (chains == 8)
+            hipLaunchKernelGGL(k_probe_fma<8>, dim3(blocks), dim3(256), 0, s, out, iters, 1.0);
+          else
+            hipLaunchKernelGGL(k_probe_fma<16>, dim3(blocks), dim3(256), 0, s, out, iters,
+                               1.0);
+        });
+        GRPIC_HIP(hipGetLastError());
+        best = std::max(best, 2.0 * chains * (double)iters * threads / (ms * 1e-3) / 1e12);
+      }
+    }
   } catch (...) {
     dfree(out);
     throw;
   }
   dfree(out);
-  *fma_tflops = 2.0 * kFmaChains * (double)iters * threads / (ms * 1e-3) / 1e12;
-  // copy: 2 x 1 GiB buffers, read + write counted
-  const long n = (1L << 30) / (long)sizeof(double2);
-  double2* a = dalloc<double2>(n);
-  double2* b = nullptr;
+  *fma_tflops = best;
+  // copy: 2 x 1 GiB buffers, read + write counted; 4, 8 or 16 blocks per
+  // compute unit, cached or nontemporal, and the runtime's copy; the best
+  const long n = (1L << 30) / (long)sizeof(dvec2);
+  dvec2* a = dalloc<dvec2>(n);
+  dvec2* b = nullptr;
+  best = 0.0;
   try {
-    b = dalloc<double2>(n);
-    const unsigned cb = (unsigned)c->num_cus * 8;
-    GRPIC_HIP(hipMemsetAsync(a, 0, n * sizeof(double2), s));
-    ms = mean_ms(s, 2, 10, [&] {
-      hipLaunchKernelGGL(k_probe_copy, dim3(cb), dim3(256), 0, s, a, b, n);
+    b = dalloc<dvec2>(n);
+    GRPIC_HIP(hipMemsetAsync(a, 0, n * sizeof(dvec2), s));
+    for (int bpc : {4, 8, 16})
+      for (int nt = 0; nt < 2; ++nt) {
+        const unsigned cb = (unsigned)c->num_cus * bpc;
+        const double ms = mean_ms(s, 2, 10, [&] {
+          if (nt)
+            hipLaunchKernelGGL(k_probe_copy<true>, dim3(cb), dim3(256), 0, s, a, b, n);
+          else
+            hipLaunchKernelGGL(k_probe_copy<false>, dim3(cb), dim3(256), 0, s, a, b, n);
+        });
+        GRPIC_HIP(hipGetLastError());
+        best = std::max(best, 2.0 * (double)n * sizeof(dvec2) / (ms * 1e-3) / 1e12);
+      }
+    // and the HIP runtime's own device-to-device copy
+    const double ms = mean_ms(s, 2, 10, [&] {
+      GRPIC_HIP(hipMemcpyAsync(b, a, n * sizeof(dvec2), hipMemcpyDeviceToDevice, s));
     });
-    GRPIC_HIP(hipGetLastError());
+    best = std::max(best, 2.0 * (double)n * sizeof(dvec2) / (ms * 1e-3) / 1e12);
   } catch (...) {
     dfree(a);
     dfree(b);
@@ -101,7 +139,7 @@ void probe_peaks(grpic_ctx* c, double* fma_tflops, double* copy_tbs) {
   }
   dfree(a);
   dfree(b);
-  *copy_tbs = 2.0 * (double)n * sizeof(double2) / (ms * 1e-3) / 1e12;
+  *copy_tbs = best;
 }
 
 }  // namespace grpic
