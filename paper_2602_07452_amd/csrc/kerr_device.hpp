@@ -290,7 +290,11 @@ __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView&
   const int nr = g.nr, nrn = nr + 1, nrh = nr;
   const double lt = (th - g.th0) * g.inv_dth;
   L.qn = theta_cell<false>(g, th, lt, g.nth + 1);
-  L.qh = theta_cell<true>(g, th, lt, g.nth);
+  // the half-angle cell from the node cell: th lies in [theta_qn,
+  // theta_qn+1), so its half cell is qn at or above theta_{qn+1/2} and
+  // qn - 1 below (clamped to [0, nth - 2] like the search it replaces)
+  const int qh = th >= theta_half(g, L.qn) ? L.qn : L.qn - 1;
+  L.qh = qh < 0 ? 0 : (qh > g.nth - 2 ? g.nth - 2 : qh);
   const float lr = radial_coord(g, r);
   int pn = (int)floorf(lr), ph = (int)floorf(lr - 0.5f);
   L.pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
