@@ -77,26 +77,24 @@ __device__ __forceinline__ void fsincos(double x, double* sn, double* cs) {
 }
 
 // sin and cos of t from those of a nearby angle t0 (s0, c0): with d = t - t0
-// (exact for nearby arguments), Taylor series of sin d and cos d - 1 to d^11
-// and d^12 (truncation below 1e-18 for |d| <= 0.2) and the angle-addition
-// formulas arranged as corrections to s0, c0.  Farther angles use fsincos.
+// (exact for nearby arguments), Taylor series of sin d and cos d - 1 to d^7
+// and d^8 (the next terms are below 3e-22 relative for |d| <= 0.01, far
+// under one ulp) and the angle-addition formulas arranged as corrections to
+// s0, c0.  Farther angles (a stage or midpoint moves theta by much less
+// than 0.01 at the time steps used here) use fsincos.
 __device__ __forceinline__ void sincos_near(double t, double t0, double s0,
                                             double c0, double* sn, double* cs) {
   const double d = t - t0;
-  if (fabs(d) > 0.2) {
+  if (fabs(d) > 0.01) {
     fsincos(t, sn, cs);
     return;
   }
   const double d2 = d * d;
-  double ps = -1.0 / 39916800.0;
-  ps = 1.0 / 362880.0 + d2 * ps;
-  ps = -1.0 / 5040.0 + d2 * ps;
+  double ps = -1.0 / 5040.0;
   ps = 1.0 / 120.0 + d2 * ps;
   ps = -1.0 / 6.0 + d2 * ps;
   const double sd = fma(d * d2, ps, d);  // sin d
-  double pc = 1.0 / 479001600.0;
-  pc = -1.0 / 3628800.0 + d2 * pc;
-  pc = 1.0 / 40320.0 + d2 * pc;
+  double pc = 1.0 / 40320.0;
   pc = -1.0 / 720.0 + d2 * pc;
   pc = 1.0 / 24.0 + d2 * pc;
   pc = -0.5 + d2 * pc;
