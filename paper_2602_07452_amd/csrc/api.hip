@@ -229,6 +229,13 @@ void setup_grid(grpic_ctx* c) {
   }
   c->stn = dalloc<double>(g.nth + 1);
   c->ctn = dalloc<double>(g.nth + 1);
+  std::vector<double> sh(g.nth), ch(g.nth);
+  for (int j = 0; j < g.nth; ++j) {
+    sh[j] = sin(c->h_th[j]);
+    ch[j] = cos(c->h_th[j]);
+  }
+  c->sth = dalloc<double>(g.nth);
+  c->cth = dalloc<double>(g.nth);
   auto up = [&](void* d, const void* h, size_t b) {
     GRPIC_HIP(hipMemcpy(d, h, b, hipMemcpyHostToDevice));
   };
@@ -242,6 +249,8 @@ void setup_grid(grpic_ctx* c) {
   up(c->tab.inv_drd, fdrd.data(), sizeof(float) * (g.nr + 1));
   up(c->stn, st.data(), sizeof(double) * (g.nth + 1));
   up(c->ctn, ct.data(), sizeof(double) * (g.nth + 1));
+  up(c->sth, sh.data(), sizeof(double) * g.nth);
+  up(c->cth, ch.data(), sizeof(double) * g.nth);
 }
 #pragma clang fp contract(on)
 
@@ -300,6 +309,8 @@ void free_all(grpic_ctx* c) {
   dfree(c->idrh);
   dfree(c->stn);
   dfree(c->ctn);
+  dfree(c->sth);
+  dfree(c->cth);
   for (int t = 0; t < 4; ++t) {
     dfree(c->tab.krr[t]);
     dfree(c->tab.ktt[t]);

@@ -510,8 +510,8 @@ __device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const do
   const double ur = P.ur[k], ut = P.uth[k], up = P.uph[k];
   Met m;
   metric(g.a, r, th, m);
-  const double Gam = sqrt(1.0 + m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
-                          2.0 * m.irp * ur * up);
+  const double Gam = fsqrt(1.0 + m.irr * ur * ur + m.itt * ut * ut + m.ipp * up * up +
+                           2.0 * m.irp * ur * up);
   const double aG = m.alpha / Gam;
   const double vr = aG * (m.irr * ur + m.irp * up) - m.betar;
   const double vt = aG * m.itt * ut;
@@ -550,9 +550,9 @@ __device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const do
     const double tc = fmin(fmax(th, g.th[0]), g.th[A.nth - 1]);
     int qt = tc >= g.th[q] ? q : q - 1;
     qt = qt < 0 ? 0 : (qt > A.nth - 2 ? A.nth - 2 : qt);
-    double sc, cc, sa, ca;
-    fsincos(tc, &sc, &cc);
-    fsincos(g.th[qt], &sa, &ca);
+    double sc = st, cc = ct;  // tc is th unless th lies outside the half angles
+    if (tc != th) fsincos(tc, &sc, &cc);
+    const double sa = g.sth[qt], ca = g.cth[qt];
     double W[4];
     dep_weights_box(g, r, tc, sc, cc, g.rn[p], g.rn[p + 1], g.th[qt], g.th[qt + 1], sa, ca,
                     W);

@@ -100,6 +100,7 @@ struct grpic_ctx {
   double *rn = nullptr, *rh = nullptr, *tn = nullptr, *th = nullptr;
   double *idrn = nullptr, *idrh = nullptr;
   double *stn = nullptr, *ctn = nullptr;  // sin, cos of the node angles
+  double *sth = nullptr, *cth = nullptr;  // sin, cos of the half angles
   grpic::Tables tab{};
   // field levels
   grpic::Level3 D[3]{};  // index: 0 = Dn, 1 = Dh0, 2 = Dh1

@@ -168,6 +168,7 @@ struct GridView {
   const double *rn, *rh, *tn, *th;  // coordinates
   const double *idrn, *idrh;        // 1/(rn[i+1]-rn[i]), 1/(rh[i+1]-rh[i])
   const double *stn, *ctn;          // sin, cos of the node angles
+  const double *sth, *cth;          // sin, cos of the half angles
   float inv_rin_f, l2_dlnr_f;       // 1/r_in, ln(2)/dlnr for the estimate
 };
 
@@ -199,6 +200,8 @@ inline GridView make_grid_view(const grpic_ctx* c) {
   g.idrh = c->idrh;
   g.stn = c->stn;
   g.ctn = c->ctn;
+  g.sth = c->sth;
+  g.cth = c->cth;
   g.inv_rin_f = (float)(1.0 / c->cfg.r_in);
   g.l2_dlnr_f = c->dlnr > 0 ? (float)(0.6931471805599453 / c->dlnr) : 0.0f;
   return g;
