@@ -41,6 +41,17 @@ __device__ __forceinline__ double fsqrt_lo(double x) {
   return fma(s, r, s);
 }
 
+// 1/sqrt(x) for finite x > 0 away from the denormal range: the hardware
+// estimate refined by two Newton steps y <- y + y (1/2 - (x/2) y^2)
+__device__ __forceinline__ double frsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double r = fma(-h * y, y, 0.5);
+  y = fma(y, r, y);
+  r = fma(-h * y, y, 0.5);
+  return fma(y, r, y);
+}
+
 // sin and cos of x for |x| < 100 (polar angles here lie near [0, pi]):
 // Cody-Waite reduction x = k pi/2 + t with pi/2 split in two parts, t in
 // [-pi/4, pi/4]; Taylor polynomials of degree 17 (sin) and 16 (cos), whose

@@ -91,10 +91,14 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      double* pw, double* e = nullptr) {
   const double a = A.a, a2 = a * a, r = z[0], ur = z[3], ut = z[4], up = z[5];
   const double s2 = s * s, sc = s * c;
-  const double rho2 = r * r + a2 * c * c, S = rho2 + 2.0 * r;
-  const double irho2 = rcp(rho2), iS = rcp(S), is2 = rcp(s2);
-  const double ixi = rho2 * iS, alpha = fsqrt(ixi), betar = 2.0 * r * iS;
-  const double sg = fabs(s) * fsqrt(rho2 * S);
+  // one inverse square root y = (rho2 S)^(-1/2) gives alpha = sqrt(rho2 / S)
+  // = rho2 y, sqrt(gamma) = |sin| rho2 S y and its inverse, 1/S = rho2 y^2
+  // and 1/rho2 = S y^2
+  const double rho2 = r * r + a2 * c * c, S = rho2 + 2.0 * r, P = rho2 * S;
+  const double y = frsq(P), y2 = y * y, is2 = rcp(s2);
+  const double irho2 = S * y2, iS = rho2 * y2;
+  const double ixi = rho2 * iS, alpha = rho2 * y, betar = 2.0 * r * iS;
+  const double sg = fabs(s) * (P * y), isg = y * fabs(s) * is2;
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
   const bool charged = GRID && qm != 0.0;
   GatherLoads gl;
@@ -102,7 +106,7 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
     if constexpr (SPLIT)
       gather_issue(A.g, A.f, r, z[1], gl);
     else
-      gather(A.g, A.f, r, z[1], rcp(sg), D, B);
+      gather(A.g, A.f, r, z[1], isg, D, B);
   }
   // contravariant momentum gamma^ij u_j and the Lorentz factor
   const double irp = a * irho2;
@@ -125,7 +129,7 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double gr = dxr * Cq + aiG * r * i4 * Aq;
   const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
   if constexpr (SPLIT) {
-    if (charged) gather_finish(A.g, A.f, r, z[1], rcp(sg), gl, D, B);
+    if (charged) gather_finish(A.g, A.f, r, z[1], isg, gl, D, B);
   }
   if (qm != 0.0) {
     // Lorentz force: alpha (q/m) [gamma_ij D^j + sqrt(g) eta_ijk U^j B^k / Gamma]
