@@ -113,7 +113,8 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double Ur = (a2 * s2 * irho2 + ixi) * ur + irp * up;
   const double Ut = irho2 * ut;
   const double Up = irp * ur + irho2 * is2 * up;
-  const double G = fsqrt(1.0 + ur * Ur + ut * Ut + up * Up), iG = rcp(G);
+  const double G2 = 1.0 + ur * Ur + ut * Ut + up * Up;
+  const double iG = frsq(G2), G = G2 * iG;  // 1/Gamma and Gamma
   const double aiG = alpha * iG;
   if (e) *e = alpha * G - betar * ur;
   f[0] = aiG * Ur - betar;
