@@ -48,7 +48,8 @@ __device__ __forceinline__ void dep_weights_box(const GridView& g, double r, dou
   double h1t = (th - ta) * (1.0 / 3.0), h2t = (tb - th) * (1.0 / 3.0);
   // 7 radii ra + i h1r (i = 0..2), r, r + i h2r (i = 1..3), and 7 angles the
   // same way; the rows are visited in order and their angles advanced by the
-  // angle-addition recurrence of sincos_steps (few values live at a time)
+  // angle-addition recurrence of sincos_steps (few values live at a time;
+  // both loops unroll, so each row's trapezoid weights are constants)
   const double h1t2 = h1t * h1t, h2t2 = h2t * h2t;
   const double sh1 = h1t * (1.0 - h1t2 * (1.0 / 6.0) * (1.0 - h1t2 * (1.0 / 20.0) *
                      (1.0 - h1t2 * (1.0 / 42.0) * (1.0 - h1t2 * (1.0 / 72.0)))));
@@ -61,7 +62,7 @@ __device__ __forceinline__ void dep_weights_box(const GridView& g, double r, dou
   // trapezoid weights along each half: (1/2, 1, 1, 1/2)
   double Vaa = 0.0, Vba = 0.0, Vab = 0.0, Vbb = 0.0;
   double Sj = sq, Cj = cq;
-#pragma unroll 1
+#pragma unroll
   for (int j = 0; j < 7; ++j) {
     if (j == 3) {
       Sj = st;
