@@ -35,12 +35,15 @@ __device__ __forceinline__ double rcp(double x) { return frcp(x); }
 __device__ __forceinline__ void metric_sc(double a, double r, double s, double c, Met& m) {
   double a2 = a * a, s2 = s * s;
   double rho2 = r * r + a2 * c * c;
-  double S = rho2 + 2.0 * r;
-  double irho2 = rcp(rho2), iS = rcp(S);
+  double S = rho2 + 2.0 * r, P = rho2 * S;
+  // y = (rho2 S)^(-1/2): 1/rho2 = S y^2, 1/S = rho2 y^2, alpha = rho2 y,
+  // sqrt(gamma) = |sin| rho2 S y
+  double y = frsq(P), y2 = y * y;
+  double irho2 = S * y2, iS = rho2 * y2;
   double ixi = rho2 * iS, xi = S * irho2;
   m.s = s;
   m.c = c;
-  m.alpha = fsqrt(ixi);
+  m.alpha = rho2 * y;
   m.betar = 2.0 * r * iS;
   m.grr = xi;
   m.gtt = rho2;
@@ -50,7 +53,7 @@ __device__ __forceinline__ void metric_sc(double a, double r, double s, double c
   m.itt = irho2;
   m.irp = a * irho2;
   m.ipp = irho2 * rcp(s2);
-  m.sg = fabs(s) * fsqrt(rho2 * S);
+  m.sg = fabs(s) * (P * y);
 }
 
 __device__ __forceinline__ void metric(double a, double r, double th, Met& m) {
@@ -64,10 +67,11 @@ __device__ __forceinline__ void metric_d_sc(double a, double r, double s, double
                                             Met& m, DMet& d) {
   double a2 = a * a, s2 = s * s, sc = s * c;
   double rho2 = r * r + a2 * c * c;
-  double S = rho2 + 2.0 * r;
-  double irho2 = rcp(rho2), iS = rcp(S), is2 = rcp(s2);
+  double S = rho2 + 2.0 * r, P = rho2 * S;
+  double y = frsq(P), y2 = y * y;  // as in metric_sc
+  double irho2 = S * y2, iS = rho2 * y2, is2 = rcp(s2);
   double ixi = rho2 * iS, xi = S * irho2;
-  double alpha = fsqrt(ixi);
+  double alpha = rho2 * y;
   m.s = s;
   m.c = c;
   m.alpha = alpha;
@@ -80,7 +84,7 @@ __device__ __forceinline__ void metric_d_sc(double a, double r, double s, double
   m.itt = irho2;
   m.irp = a * irho2;
   m.ipp = irho2 * is2;
-  m.sg = fabs(s) * fsqrt(rho2 * S);
+  m.sg = fabs(s) * (P * y);
   double i4 = irho2 * irho2, ixi2 = ixi * ixi;
   double dr2[2] = {2.0 * r, -2.0 * a2 * sc};
   double dxi[2] = {2.0 * irho2 * (1.0 - 2.0 * r * r * irho2),
