@@ -430,6 +430,135 @@ def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
     return out
 
 
+def timed_steps(ctx, steps, timing):
+    """Run `steps` steps between two stream synchronisations; with timing, the
+    library's HIP events time each kernel group on its stream.  Particle-steps
+    count the particles alive at the start and at the end (mean)."""
+    ctx.enable_timing(timing)
+    ctx.reset_timings()
+    ctx.sync()
+    d0 = ctx.diagnostics()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    t1 = time.perf_counter()
+    d1 = ctx.diagnostics()
+    tim = ctx.timings() if timing else {}
+    ctx.enable_timing(False)
+    alive = 0.5 * (d0["alive"] + d1["alive"])
+    return {"steps": steps, "seconds": t1 - t0, "d0": d0, "d1": d1, "tim": tim,
+            "alive": alive, "value": alive * steps / (t1 - t0),
+            "ms_step": (t1 - t0) * 1e3 / max(steps, 1)}
+
+
+def warm_and_time(ctx, args, graph, W):
+    """Warmup steps, the autotuner's trials (real, untimed steps), then the
+    timed steps; returns the timed run and the autotuner's choice."""
+    ctx.use_graph(graph)
+    ctx.step(args.warmup)
+    ctx.sync()
+    tune = None
+    if not args.no_autotune:
+        tune = ctx.autotune(3)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    run = timed_steps(ctx, args.steps, timing=not graph)
+    return run, tune
+
+
+def flop_counts(W, run):
+    """Algorithmic FP64 operations of the explicit and implicit pushes over a
+    run, from the per-particle counts and the run's scheme and iteration
+    statistics."""
+    d0, d1 = run["d0"], run["d1"]
+    steps, alive = run["steps"], run["alive"]
+    impl = d1["implicit_steps"] - d0["implicit_steps"]
+    iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
+    evolve = W["mode"] == "evolve"
+    grid = W["mode"] != "none"
+    flop_rk4 = FLOP_RK4 if grid else FLOP_RK4 - 4 * FLOP_GATHER
+    n_eval = 7 if W.get("solver") == "newton" else 1
+    flop_iter = n_eval * (FLOP_EVAL if grid else FLOP_EVAL - FLOP_GATHER) + \
+        (FLOP_NEWTON_EXTRA if n_eval > 1 else FLOP_IMR_EXTRA)
+    return {
+        "push": steps * alive * (flop_rk4 + FLOP_SWITCH) +
+        (steps * alive - impl) * (FLOP_WEIGHTS if evolve else 0),
+        "implicit": iters * flop_iter + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
+    }, impl, iters
+
+
+def roofline(W, run, workload):
+    """Each kernel group's achieved rate against its bound, from the HIP-event
+    timings of `run` (None without timings); the dominant group is the top
+    level."""
+    tim = run["tim"]
+    if not tim:
+        return None
+    flops, _, _ = flop_counts(W, run)
+    alive = run["alive"]
+    paper = W.get("deposit") == "paper"
+    bytes_dep = BYTES_DEPOSIT_PAPER if paper else BYTES_DEPOSIT
+    # counter summaries are taken on the default configuration of a workload
+    wl_key = workload + ("_paper" if paper else "") + \
+        ("_clean" if W.get("clean_every") else "") + ("_inject" if W.get("inj_every") else "") + \
+        ("_newton" if W.get("solver") == "newton" else "")
+    nodes = (W["nr"] + 1) * (W["nth"] + 1)
+    groups = {}
+    for grp in ("push", "implicit", "deposit", "fields", "clean"):
+        cnt_g = tim.get(grp, (0.0, 0))[1]
+        if cnt_g == 0:
+            continue
+        avg_g = tim[grp][0] / cnt_g * 1e-3
+        if grp in ("push", "implicit"):
+            a_g = flops[grp] / cnt_g / avg_g / 1e12
+            groups[grp] = {"bound": "alu", "achieved": a_g, "peak": PEAK_FP64_TFLOPS,
+                           "unit": "TFLOP/s", "frac": a_g / PEAK_FP64_TFLOPS,
+                           "flop_per_launch": flops[grp] / cnt_g}
+        else:
+            nb = {"deposit": bytes_dep * alive,
+                  "fields": BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"],
+                  "clean": 2 * nodes * (BYTES_CLEAN_SWEEP * W.get("clean_iters", 500) +
+                                        BYTES_CLEAN_FIXED)}[grp]
+            a_g = nb / avg_g / 1e9
+            groups[grp] = {"bound": "hbm", "achieved": a_g, "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": a_g / PEAK_HBM_GBS,
+                           "bytes_per_launch": nb}
+        groups[grp]["avg_launch_ms"] = avg_g * 1e3
+        groups[grp]["launches"] = cnt_g
+        groups[grp]["traffic"] = counter_traffic(grp, wl_key, W["n"])
+    ms = {g: tim[g][0] for g in groups if g != "clean"}
+    dom = max(ms, key=ms.get)
+    roof = {"kernel": dom, **groups[dom]}
+    roof["algorithmic_bytes"] = (BYTES_PUSH * alive if dom == "push" else
+                                 groups[dom].get("bytes_per_launch"))
+    roof["groups"] = groups
+    roof["kernel_ms_per_step"] = {k: v[0] / max(run["steps"], 1) for k, v in tim.items()
+                                  if v[1] > 0}
+    return roof
+
+
+def plain_guess_run(G, W, args, pre_steps):
+    """The same workload with the plain start of the implicit iteration (the
+    hybrid's RK4 result, no network), run through the same number of steps
+    before its timed region, for the learned-vs-plain comparison."""
+    Wp = dict(W)
+    Wp.pop("guess", None)
+    ctx, _ = make_context(G, Wp, push_wps=args.push_wps,
+                          persistent_waves=args.persistent_waves)
+    try:
+        if pre_steps:
+            ctx.step(pre_steps)
+        run, _ = warm_and_time(ctx, args, bool(args.graph or W.get("graph", 0)), Wp)
+    finally:
+        ctx.close()
+    d0, d1 = run["d0"], run["d1"]
+    impl = d1["implicit_steps"] - d0["implicit_steps"]
+    iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
+    return {"value": run["value"], "unit": "particle-steps/s", "ms_per_step": run["ms_step"],
+            "implicit_fraction": impl / max(run["steps"] * run["alive"], 1),
+            "mean_implicit_iterations": float(iters / max(impl, 1)),
+            "h_error": herr_percentiles(d1["herr_hist"])}
+
+
 def copy_calibration(nbytes):
     """One device-to-device copy of nbytes with the HIP runtime's own blit
     kernel: a kernel of known traffic for scaling the FETCH_SIZE / WRITE_SIZE
@@ -453,7 +582,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--particles", type=int, default=0, help="override particle count")
     ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
     ap.add_argument("--push-wps", type=int, default=0, help="explicit-push waves per SIMD")
@@ -481,6 +610,13 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain guess comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--learned-dt", type=float, nargs="+", default=[0.01, 0.1],
+                    help="time steps of the learned-vs-plain comparison on the charged "
+                         "test-particle workload")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain-start run of a learned-guess workload")
+    ap.add_argument("--roofline-steps", type=int, default=20,
+                    help="eager steps timed per kernel group after graph-replayed steps")
     ap.add_argument("--table2-t", type=float, default=1000.0,
                     help="end time of the Table 2 scheme runs (workload c1; 0 skips them)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -525,109 +661,36 @@ def main():
           flush=True)
     graph = bool(args.graph or W.get("graph", 0))
     mlp_info = None
+    pre_steps = 0
     if W.get("guess") == "mlp":
         # learned guess: trained on the GPU on the converged implicit steps of
         # the first warmup steps (RK4 result corrected by the network)
+        pre_steps = max(args.warmup // 2, 4)
+        t0 = time.perf_counter()
         ctx.mlp_collect(1 << 24)
-        ctx.step(max(args.warmup // 2, 4))
+        ctx.step(pre_steps)
         ctx.mlp_collect(0)
         loss = ctx.mlp_train(epochs=8, batch=4096, lr=3e-3, lr_final=3e-5, seed=7)
-        mlp_info = {"samples": ctx.mlp_num_samples(), "loss_first_epoch": float(loss[0]),
-                    "loss_last_epoch": float(loss[-1])}
-    ctx.use_graph(graph)
-    ctx.step(args.warmup)
-    ctx.sync()
-    tune = None
-    if not args.no_autotune:
-        # launch settings picked by the autotuner (its trials are untimed steps)
-        tune = ctx.autotune(3)
-        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
-    n_alive = ctx.diagnostics()["alive"] or W["n"]
-    ctx.enable_timing(not graph)
-    ctx.reset_timings()
-    d0 = ctx.diagnostics()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    ctx.sync()
-    t1 = time.perf_counter()
-    d1 = ctx.diagnostics()
-    tim = ctx.timings()
-    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
-    if W.get("inj_every"):
-        # injection grows the particle count over the timed steps
-        n_alive = 0.5 * (n_alive + d1["alive"])
-    value = n_alive * args.steps / (t1 - t0)
+        mlp_info = {"samples": ctx.mlp_num_samples(), "epochs": 8,
+                    "loss_first_epoch": float(loss[0]), "loss_last_epoch": float(loss[-1]),
+                    "collect_and_train_s": time.perf_counter() - t0}
+    run, tune = warm_and_time(ctx, args, graph, W)
+    value, ms_step = run["value"], run["ms_step"]
     print(f"[bench] {ms_step:.3f} ms/step, {value:.4e} particle-steps/s", file=sys.stderr,
           flush=True)
-
-    # dominant kernel and its roofline
-    impl = d1["implicit_steps"] - d0["implicit_steps"]
-    iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
-    evolve = W["mode"] == "evolve"
-    grid = W["mode"] != "none"
-    flop_rk4 = FLOP_RK4 if grid else FLOP_RK4 - 4 * FLOP_GATHER
-    n_eval = 7 if W.get("solver") == "newton" else 1
-    flop_iter = n_eval * (FLOP_EVAL if grid else FLOP_EVAL - FLOP_GATHER) + \
-        (FLOP_NEWTON_EXTRA if n_eval > 1 else FLOP_IMR_EXTRA)
-    flops = {
-        "push": args.steps * n_alive * (flop_rk4 + FLOP_SWITCH) +
-        (args.steps * n_alive - impl) * (FLOP_WEIGHTS if evolve else 0),
-        "implicit": iters * flop_iter + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
-    }
-    roof = None
-    paper = W.get("deposit") == "paper"
-    bytes_dep = BYTES_DEPOSIT_PAPER if paper else BYTES_DEPOSIT
-    # counter summaries are taken on the default configuration of a workload
-    wl_key = args.workload + ("_paper" if paper else "") + \
-        ("_clean" if W.get("clean_every") else "") + ("_inject" if W.get("inj_every") else "") + \
-        ("_newton" if W.get("solver") == "newton" else "")
-    if not graph:
-        ms = {k: v[0] for k, v in tim.items()
-              if k in ("push", "implicit", "deposit", "fields") and v[1] > 0}
-        dom = max(ms, key=ms.get)
-        cnt = max(tim[dom][1], 1)
-        avg_s = ms[dom] / cnt * 1e-3
-        if dom in ("push", "implicit"):
-            achieved = flops[dom] / cnt / avg_s / 1e12
-            roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
-                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_TFLOPS,
-                    "traffic": counter_traffic(dom, wl_key, W["n"]),
-                    "avg_launch_ms": avg_s * 1e3}
-        else:
-            nbytes = (bytes_dep * n_alive if dom == "deposit"
-                      else BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"])
-            achieved = nbytes / avg_s / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                    "traffic": counter_traffic(dom, wl_key, W["n"]),
-                    "avg_launch_ms": avg_s * 1e3}
-        roof["algorithmic_bytes"] = BYTES_PUSH * n_alive if dom == "push" else None
-        # every timing group against its own bound (per launch)
-        groups = {}
-        for grp in ("push", "implicit", "deposit", "fields", "clean"):
-            cnt_g = tim.get(grp, (0.0, 0))[1]
-            if cnt_g == 0:
-                continue
-            avg_g = tim[grp][0] / cnt_g * 1e-3
-            if grp in ("push", "implicit"):
-                a_g = flops[grp] / cnt_g / avg_g / 1e12
-                groups[grp] = {"bound": "alu", "achieved": a_g, "peak": PEAK_FP64_TFLOPS,
-                               "unit": "TFLOP/s", "frac": a_g / PEAK_FP64_TFLOPS}
-            else:
-                nodes = (W["nr"] + 1) * (W["nth"] + 1)
-                nb = {"deposit": bytes_dep * n_alive,
-                      "fields": BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"],
-                      "clean": 2 * nodes * (BYTES_CLEAN_SWEEP * W.get("clean_iters", 500) +
-                                            BYTES_CLEAN_FIXED)}[grp]
-                a_g = nb / avg_g / 1e9
-                groups[grp] = {"bound": "hbm", "achieved": a_g, "peak": PEAK_HBM_GBS,
-                               "unit": "GB/s", "frac": a_g / PEAK_HBM_GBS}
-            groups[grp]["avg_launch_ms"] = avg_g * 1e3
-            groups[grp]["traffic"] = counter_traffic(grp, wl_key, W["n"])
-        roof["groups"] = groups
-        roof["kernel_ms_per_step"] = {k: v[0] / max(args.steps, 1) for k, v in tim.items()
-                                      if v[1] > 0}
+    # roofline: HIP-event timing of each kernel group on the library's stream.
+    # Events cannot be placed between the kernels of a replayed graph, so with
+    # graph replay the groups are timed over eager steps of the same kernels
+    # that follow the timed region.
+    if graph:
+        ctx.use_graph(False)
+        rl = timed_steps(ctx, max(1, min(args.steps, args.roofline_steps)), timing=True)
+    else:
+        rl = run
+    roof = roofline(W, rl, args.workload)
+    if roof is not None and graph:
+        roof["timing"] = (f"HIP events over {rl['steps']} eager steps after the "
+                          f"{args.steps} graph-replayed timed steps")
 
     peaks = None
     if not args.no_probe:
@@ -641,6 +704,19 @@ def main():
                         else peaks["copy_tbs"] * 1e3)
                 gd["frac_of_measured"] = gd["achieved"] / ceil
     ctx.close()
+    d0, d1 = run["d0"], run["d1"]
+    impl = d1["implicit_steps"] - d0["implicit_steps"]
+    iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
+    grid = W["mode"] != "none"
+    plain = None
+    if mlp_info is not None and not args.no_plain:
+        # learned vs plain on the workload itself: the same run with the
+        # iteration started from the RK4 result alone
+        print("[bench] same workload, plain implicit start", file=sys.stderr, flush=True)
+        plain = plain_guess_run(G, W, args, pre_steps)
+        plain["learned_over_plain"] = value / plain["value"]
+        print(f"[bench] plain start: {plain['ms_per_step']:.3f} ms/step "
+              f"(learned/plain {plain['learned_over_plain']:.3f})", file=sys.stderr, flush=True)
     table2 = ratios = None
     if args.workload == "c1" and args.table2_t > 0:
         table2 = table2_runs(G, W, args.table2_t)
@@ -648,7 +724,8 @@ def main():
     learned = None
     if not args.no_learned:
         print("[bench] learned vs plain implicit guess", file=sys.stderr, flush=True)
-        learned = learned_vs_plain(G, args.learned_steps)
+        learned = {f"dt={dt:g}": learned_vs_plain(G, args.learned_steps, dt=dt)
+                   for dt in args.learned_dt}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -659,7 +736,8 @@ def main():
         "metric": "particle-steps/s (gather+push+deposit) at fixed H error; learned vs plain guess",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 particles / f32 fields" if grid else "f64",
         "data": "synthetic",
         "config": {"workload": W["desc"], "particles": W["n"], "grid": [W["nr"], W["nth"]],
                    "dt": cfg.dt,
@@ -667,10 +745,12 @@ def main():
                               else "Hyb2 (RK4 -> Hamiltonian discrete gradient)"),
                    "threshold": cfg.hyb_threshold,
                    "guess": ("RK4 result + learned correction" if mlp_info else "RK4 result"),
-                   "fields": "FP32" if grid else "none", "particle_state": "FP64",
+                   "precision": ("FP64 particle state, metric, push and energy check; FP32 "
+                                 "field storage, Maxwell arithmetic and J/rho outputs; int64 "
+                                 "fixed-point deposit sums") if grid else "FP64",
                    "graph": graph, "sort_every": cfg.sort_every,
                    "tile": [cfg.tile_r, cfg.tile_th]},
-        "implicit_fraction": impl / max(args.steps * n_alive, 1),
+        "implicit_fraction": impl / max(args.steps * run["alive"], 1),
         "mean_implicit_iterations": float(iters / max(impl, 1)),
         "h_error": herr_percentiles(d1["herr_hist"]),
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
@@ -678,6 +758,7 @@ def main():
         "measured_peaks": peaks,
         "autotune": tune,
         "learned_guess_training": mlp_info,
+        "plain_guess": plain,
         "learned_guess": learned,
         "table2_a0": table2,
         "pusher_cost_ratios": ratios,
