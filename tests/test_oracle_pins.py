@@ -874,6 +874,76 @@ def test_poynting_vanishes_for_static_schwarzschild_wald():
     assert vals[1] < vals[0] / 3 or vals[1] < 1e-14
 
 
+def _fields_for_EH(a, r, th, EH):
+    """D^i, B^i (contravariant, plain) whose electric and magnetic fields
+    E_i, H_i (covariant) are the given EH = (E_r, E_th, E_ph, H_r, H_th, H_ph)
+    at (r, th): the constitutive relations of eq. Ei and its H analogue,
+    E_i = alpha gamma_ij D^j + e_ijk beta^j B^k and
+    H_i = alpha gamma_ij B^j - e_ijk beta^j D^k with e_ijk = sqrt(gamma)
+    eta_ijk (eta_{r th ph} = +1) and beta = (beta^r, 0, 0), inverted as one
+    6 x 6 linear system."""
+    m = O.metric(a, r, th)
+    alpha, betar, sg = m[0], m[1], m[10]
+    gam = np.array([[m[2], 0, m[5]], [0, m[3], 0], [m[5], 0, m[4]]])
+    X = np.zeros((3, 3))          # (beta x V)_i = X_ik V^k
+    X[1, 2] = -sg * betar         # e_{th r ph} beta^r V^ph
+    X[2, 1] = sg * betar          # e_{ph r th} beta^r V^th
+    M = np.block([[alpha * gam, X], [-X, alpha * gam]])
+    sol = np.linalg.solve(M, np.asarray(EH, np.float64))
+    return sol[:3], sol[3:]
+
+
+def _target_EH(r, th):
+    """Smooth E_i, H_i with E_th H_ph and E_ph H_th both of order one."""
+    s, c = np.sin(th), np.cos(th)
+    return (0.0, s * s * (1 + 0.3 * c) * r / (r + 1), 0.6 * s ** 3 / (1 + 0.1 * r),
+            0.0, 0.9 * s * s * (1 + 0.5 * c) * np.sqrt(r) / 3, s * s * (0.7 + 0.2 * np.cos(2 * th)) * np.exp(-r / 10))
+
+
+def test_poynting_luminosity_of_prescribed_fields():
+    """Eq. Pbz read as P(r) = (1/2) int (E_th H_ph - E_ph H_th) dtheta (the
+    factor 2 pi / 4 pi of the phi integral and the Gaussian Poynting vector):
+    D and B are built on every Yee point from prescribed smooth E_i, H_i by
+    inverting the constitutive relations, and the oracle's luminosity at
+    interior radii converges at second order to the integral of the
+    prescribed fields, positive for an outgoing flux.  A wrong factor, sign,
+    or an average taken from the wrong Yee points fails this."""
+    a = 0.9
+    i_frac = 0.5  # the radius r_{N/2}, common to every resolution
+    errs, vals = [], []
+    for N in (24, 48, 96):
+        g = O.Grid(a, N, N, 1.9, 12.0)
+        D = [g.zeros(c) for c in range(3)]
+        B = [g.zeros(3 + c) for c in range(3)]
+        # Yee points of each component (row = theta index, column = r index)
+        pts = {0: (g.rh, g.tn), 1: (g.rn, g.th), 2: (g.rn, g.tn),
+               3: (g.rn, g.th), 4: (g.rh, g.tn), 5: (g.rh, g.th)}
+        for c in range(6):
+            rr, tt = pts[c]
+            arr = D[c] if c < 3 else B[c - 3]
+            for j, t in enumerate(tt):
+                for i, r in enumerate(rr):
+                    d, b = _fields_for_EH(a, r, t, _target_EH(r, t))
+                    arr[j, i] = d[c] if c < 3 else b[c - 3]
+        P = O.poynting(g, D, B)
+        i = int(i_frac * N)
+        r = g.rn[i]
+
+        def flux(t):
+            E = _target_EH(r, t)
+            return 0.5 * (E[1] * E[5] - E[2] * E[4])
+        exact, _ = integrate.quad(flux, g.th0, np.pi - g.th0, epsabs=1e-14, epsrel=1e-13)
+        # both terms matter: the second is a sizeable fraction of the first
+        t1, _ = integrate.quad(lambda t: 0.5 * _target_EH(r, t)[1] * _target_EH(r, t)[5],
+                               g.th0, np.pi - g.th0)
+        assert 0.2 < (t1 - exact) / t1 < 0.9
+        errs.append(abs(P[i] - exact) / abs(exact))
+        vals.append((P[i], exact))
+    assert all(p > 0 and e > 0 for p, e in vals)
+    assert errs[-1] < 2e-3
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
 # ------------------------------------------------------ pair injection
 def _inj_params(r0=2.0, r1=6.0, mult=3.0, density=5.0, theta=0.5, seed=99):
     return O.InjectParams(r0, r1, mult, density, theta, seed)
