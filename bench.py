@@ -23,22 +23,27 @@ SEED = 2602074520
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 FLOP/clk)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
-# Algorithmic FP64 operations per particle, counted on the formulas the push
-# evaluates (+, -, *, / and sqrt = 1; fused a*b+c = 2; sin, cos, log = 1).
-FLOP_METRIC_D = 89     # metric + derivatives of alpha, beta^r, gamma^ij
-FLOP_GATHER = 76       # cell location + 6 metric-weighted bilinear reads
-FLOP_RHS = 93          # Gamma, dx/dt, gravity + Lorentz acceleration, power
-FLOP_ENERGY = 43       # e = alpha Gamma - beta^r u_r at one state
-FLOP_RK4_COMB = 90     # stage states and the weighted sum
-FLOP_IMR_EXTRA = 42    # midpoint state, update, convergence test
-FLOP_WEIGHTS = 610     # 7 x 7 sqrt(gamma) samples, trapezoid sub-volumes, cell
-FLOP_EVAL = FLOP_METRIC_D + FLOP_GATHER + FLOP_RHS
-FLOP_RK4 = 4 * FLOP_EVAL + FLOP_RK4_COMB
-FLOP_SWITCH = 2 * FLOP_ENERGY + 4
-FLOP_IMR_ITER = FLOP_EVAL + FLOP_IMR_EXTRA
-# Newton (solver "newton"): the base and six perturbed evaluations, the 6 x 6
-# Jacobian (108), elimination with pivoting and back substitution (~220)
-FLOP_NEWTON_EXTRA = 108 + 220 + FLOP_IMR_EXTRA
+# Algorithmic FP64 operations per particle, measured on the oracle compiled
+# with a counting scalar type (oracle/flopcount.cpp, split-monopole and
+# neutral-orbit workloads): additions, subtractions and multiplications count
+# one each, and so do divisions, square roots and sin/cos/exp/log calls (their
+# numbers are listed apart by the counter).  The counts follow the method as
+# the oracle writes it, e.g. the deposit weights evaluate sqrt(gamma) at all
+# 4 x 16 trapezoid points with their own sin/cos, where the kernel shares the
+# 7 x 7 distinct samples; the kernel's own shared-sample formulation needs
+# fewer operations (FLOP_KERNEL_* below, counted by hand on its formulas).
+FLOP_RK4_GRID = 1779     # RK4 step with the six fields gathered at every stage
+FLOP_RK4_NOGRID = 959    # RK4 step of a neutral particle (no fields)
+FLOP_ENERGY = 55         # e = alpha Gamma - beta^r u_r at one state
+FLOP_WEIGHTS = 1311      # deposit weights of a position (eqs. v1-v5)
+FLOP_IMR_ITER = 455      # one Picard iteration of eq. imr1 (gather included)
+FLOP_NEWTON_ITER = 3400  # one Newton iteration (seven evaluations, 6 x 6 solve)
+FLOP_HAM_ITER = 3680     # one discrete-gradient iteration (six orderings)
+FLOP_GATHER = 145        # one metric-weighted gather of the six components
+FLOP_SWITCH = 2 * FLOP_ENERGY + 3
+# hand counts of the kernel's formulation (shared samples, factored forms)
+FLOP_KERNEL_RK4_GRID = 4 * (89 + 76 + 93) + 90
+FLOP_KERNEL_WEIGHTS = 610
 # algorithmic HBM bytes per particle of the explicit push pass: state in/out
 # (2 x 48), q/m, flags, H0, herr in/out, iterations, old position + dphi,
 # new weights (three stored, the fourth is their complement) + cell
@@ -475,14 +480,21 @@ def flop_counts(W, run):
     iters = (d1["iter_hist"] - d0["iter_hist"]) @ np.arange(len(d1["iter_hist"]))
     evolve = W["mode"] == "evolve"
     grid = W["mode"] != "none"
-    flop_rk4 = FLOP_RK4 if grid else FLOP_RK4 - 4 * FLOP_GATHER
-    n_eval = 7 if W.get("solver") == "newton" else 1
-    flop_iter = n_eval * (FLOP_EVAL if grid else FLOP_EVAL - FLOP_GATHER) + \
-        (FLOP_NEWTON_EXTRA if n_eval > 1 else FLOP_IMR_EXTRA)
+    flop_rk4 = FLOP_RK4_GRID if grid else FLOP_RK4_NOGRID
+    if not grid:
+        flop_iter = FLOP_HAM_ITER  # neutral particles: discrete gradient
+    elif W.get("solver") == "newton":
+        flop_iter = FLOP_NEWTON_ITER
+    else:
+        flop_iter = FLOP_IMR_ITER
     return {
         "push": steps * alive * (flop_rk4 + FLOP_SWITCH) +
         (steps * alive - impl) * (FLOP_WEIGHTS if evolve else 0),
         "implicit": iters * flop_iter + impl * (FLOP_SWITCH + (FLOP_WEIGHTS if evolve else 0)),
+        # the same work counted on the kernel's own shared-sample formulation
+        "push_kernel_count": steps * alive * ((FLOP_KERNEL_RK4_GRID if grid else flop_rk4) +
+                                              FLOP_SWITCH) +
+        (steps * alive - impl) * (FLOP_KERNEL_WEIGHTS if evolve else 0),
     }, impl, iters
 
 
@@ -512,7 +524,11 @@ def roofline(W, run, workload):
             a_g = flops[grp] / cnt_g / avg_g / 1e12
             groups[grp] = {"bound": "alu", "achieved": a_g, "peak": PEAK_FP64_TFLOPS,
                            "unit": "TFLOP/s", "frac": a_g / PEAK_FP64_TFLOPS,
-                           "flop_per_launch": flops[grp] / cnt_g}
+                           "flop_per_launch": flops[grp] / cnt_g,
+                           "flop_count": "oracle, counting scalar type"}
+            if grp == "push":
+                groups[grp]["frac_kernel_count"] = \
+                    flops["push_kernel_count"] / cnt_g / avg_g / 1e12 / PEAK_FP64_TFLOPS
         else:
             nb = {"deposit": bytes_dep * alive,
                   "fields": BYTES_FIELDS_PER_CELL * W["nr"] * W["nth"],
