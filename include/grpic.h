@@ -332,6 +332,20 @@ int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
  * luminosity P(r_i) of eq. Pbz at every node radius (pbz may be NULL).    */
 int grpic_field_diagnostics(grpic_ctx *ctx, double *gauss_max,
                             double *divb_max, double *pbz);
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): the same results as grpic_field_diagnostics
+ * without any device allocation or free.  Its scratch (the two maxima and
+ * the N_r + 1 luminosities) is a static device array of fixed size that
+ * every GPU running the library holds until the process ends; it is set up
+ * by grpic_create on the context's device.  Limit: N_r <= 16384
+ * (GRPIC_E_INVALID above).  Calls on one GPU share that array: the library
+ * serialises its own calls (each clears the maxima, launches, copies the
+ * results to the host outputs and synchronises the context's stream before
+ * the next may start), so a call is not capturable in a graph, and work of
+ * another process on the same GPU must not overlap it.  Errors as
+ * grpic_field_diagnostics; GRPIC_E_STATE without a grid.                  */
+int grpic_field_diagnostics_noalloc(grpic_ctx *ctx, double *gauss_max,
+                                    double *divb_max, double *pbz);
 /* Divergence cleaning now (Sec. 2.4, eq. phi), as clean_every does after a
  * step: on each D chain, iters Jacobi sweeps (FP64, from phi = 0, phi = 0 on
  * the boundary nodes) of div(sqrt(g) g^kk d_k phi) = G with G the

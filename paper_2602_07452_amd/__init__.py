@@ -310,6 +310,12 @@ class Context:
         self._c("grpic_field_diagnostics", C.byref(g), C.byref(b), _dp(p))
         return g.value, b.value, p
 
+    def field_diagnostics_noalloc(self):
+        g, b = C.c_double(), C.c_double()
+        p = np.zeros(self.cfg.nr + 1)
+        self._c("grpic_field_diagnostics_noalloc", C.byref(g), C.byref(b), _dp(p))
+        return g.value, b.value, p
+
     # -- timing
     def enable_timing(self, enable=True):
         self._c("grpic_enable_timing", C.c_int(1 if enable else 0))

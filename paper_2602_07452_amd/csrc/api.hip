@@ -668,6 +668,7 @@ int grpic_create(const grpic_config* cfg, grpic_ctx** out) {
     c = new grpic_ctx();
     c->cfg = *cfg;
     GRPIC_HIP(hipGetDevice(&c->device));
+    diag_scratch_init(c->device);
     GRPIC_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount,
                                     c->device));
     GRPIC_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
@@ -1056,6 +1057,15 @@ int grpic_field_diagnostics(grpic_ctx* c, double* gauss_max, double* divb_max,
     check_ctx(c);
     if (c->nr == 0) throw Error(GRPIC_E_STATE, "context has no grid");
     launch_field_diag(c, gauss_max, divb_max, pbz);
+  });
+}
+
+int grpic_field_diagnostics_noalloc(grpic_ctx* c, double* gauss_max, double* divb_max,
+                                    double* pbz) {
+  return guarded(c, [&] {
+    check_ctx(c);
+    if (c->nr == 0) throw Error(GRPIC_E_STATE, "context has no grid");
+    field_diag_noalloc(c, gauss_max, divb_max, pbz);
   });
 }
 

@@ -209,6 +209,11 @@ void launch_sort(grpic_ctx* c);
 void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
                        double* pbz);
+// allocation-free variant: the scratch is a static device array of the
+// Maxwell translation unit; diag_scratch_init takes its address per device
+constexpr int kDiagMaxNr = 16384;  // radial cells the scratch holds at most
+void diag_scratch_init(int device);
+void field_diag_noalloc(grpic_ctx* c, double* gauss_max, double* divb_max, double* pbz);
 void launch_guess(grpic_ctx* c);
 void mlp_upload(grpic_ctx* c, const float* theta, const float* mean,
                 const float* inv_std, const float* scale);

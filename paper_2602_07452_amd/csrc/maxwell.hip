@@ -12,6 +12,9 @@
 // and a component needed off its own point is the plain average of the two
 // neighbouring G values (the metric-weighted average of the paper, times
 // sqrt(gamma) of the target point).
+#include <mutex>
+#include <string>
+
 #include "kerr_device.hpp"
 
 namespace grpic {
@@ -504,12 +507,10 @@ __global__ void k_poynting(FdArgs F, Level3 E, Level3 H, double dth,
   out[i] = 0.5 * sum;
 }
 
-void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
-                       double* pbz) {
-  float* dmax = nullptr;
-  double* dp = nullptr;
-  GRPIC_HIP(hipMalloc(&dmax, 2 * sizeof(float)));
-  GRPIC_HIP(hipMalloc(&dp, sizeof(double) * (c->nr + 1)));
+// the diagnostics into dmax[2] (FP32 maxima, cleared here) and dp[nr + 1]
+// (device), then copied to the caller's host outputs; synchronises
+static void field_diag_into(grpic_ctx* c, float* dmax, double* dp, double* gauss_max,
+                            double* divb_max, double* pbz) {
   launch_fill(c, dmax, 2 * sizeof(float));
   DiagArgs A;
   A.nr = c->nr;
@@ -535,15 +536,72 @@ void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
   GRPIC_HIP(hipGetLastError());
   float hm[2];
   GRPIC_HIP(hipMemcpyAsync(hm, dmax, sizeof(hm), hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> hp(c->nr + 1);
-  GRPIC_HIP(hipMemcpyAsync(hp.data(), dp, sizeof(double) * (c->nr + 1),
-                           hipMemcpyDeviceToHost, c->stream));
+  if (pbz)
+    GRPIC_HIP(hipMemcpyAsync(pbz, dp, sizeof(double) * (c->nr + 1), hipMemcpyDeviceToHost,
+                             c->stream));
   GRPIC_HIP(hipStreamSynchronize(c->stream));
-  GRPIC_HIP(hipFree(dmax));
-  GRPIC_HIP(hipFree(dp));
   if (gauss_max) *gauss_max = hm[0];
   if (divb_max) *divb_max = hm[1];
-  if (pbz) for (int i = 0; i <= c->nr; ++i) pbz[i] = hp[i];
+}
+
+void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
+                       double* pbz) {
+  float* dmax = nullptr;
+  double* dp = nullptr;
+  GRPIC_HIP(hipMalloc(&dmax, 2 * sizeof(float)));
+  hipError_t e = hipMalloc(&dp, sizeof(double) * (c->nr + 1));
+  if (e != hipSuccess) {
+    (void)hipFree(dmax);
+    GRPIC_HIP(e);
+  }
+  try {
+    field_diag_into(c, dmax, dp, gauss_max, divb_max, pbz);
+  } catch (...) {
+    (void)hipFree(dmax);
+    (void)hipFree(dp);
+    throw;
+  }
+  GRPIC_HIP(hipFree(dmax));
+  GRPIC_HIP(hipFree(dp));
+}
+
+// ------------------------------------------- allocation-free diagnostics
+// Scratch of grpic_field_diagnostics_noalloc: bytes [0, 8) hold the two FP32
+// maxima, bytes [256, 256 + 8 (kDiagMaxNr + 1)) the luminosities P(r_i).
+// Every device that runs the library holds its own copy until the process
+// ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in, not a device address).
+constexpr size_t kDiagScratchBytes = 256 + sizeof(double) * (kDiagMaxNr + 1);
+static __device__ __align__(256) unsigned char scratch[kDiagScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu[kScratchDevices];
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+// once per device, with that device current (called by grpic_create)
+void diag_scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu[device]);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  GRPIC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[device] = p;
+}
+
+void field_diag_noalloc(grpic_ctx* c, double* gauss_max, double* divb_max, double* pbz) {
+  if (c->nr > kDiagMaxNr)
+    throw Error(GRPIC_E_INVALID, "grid has " + std::to_string(c->nr) +
+                                     " radial cells: the allocation-free diagnostics hold "
+                                     "at most " + std::to_string(kDiagMaxNr));
+  if (c->device < 0 || c->device >= kScratchDevices || !g_scratch_ptr[c->device])
+    throw Error(GRPIC_E_STATE, "diagnostics scratch not set up on this device");
+  // calls on one device are serialised: each waits for its stream before
+  // the next one may use the shared scratch
+  std::lock_guard<std::mutex> lock(g_scratch_mu[c->device]);
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[c->device]);
+  field_diag_into(c, reinterpret_cast<float*>(base), reinterpret_cast<double*>(base + 256),
+                  gauss_max, divb_max, pbz);
 }
 
 }  // namespace grpic
