@@ -315,27 +315,37 @@ __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView&
   L.irh = g.idrh[L.ph];
 }
 
-__device__ __forceinline__ void gather_finish(const GridView& g, const FieldView& F,
-                                              double r, double th, double isg,
-                                              GatherLoads& L, double* D, double* B) {
+// Refine the estimated radial cells against the node values loaded with
+// them (one cell either way) and reload the corners when a cell changed:
+// afterwards L holds the corners, cells and radial bounds (rn0, rn1, irn,
+// rh0, rh1, irh) of the cells of (r, th).
+__device__ __forceinline__ void gather_settle(const GridView& g, const FieldView& F,
+                                              double r, GatherLoads& L) {
   const int nr = g.nr, nrn = nr + 1, nrh = nr;
   int pn = L.pn, ph = L.ph, pn2 = pn, ph2 = ph;
   if (pn > 0 && r < L.rn0) --pn2;
   else if (pn < nr - 1 && r >= L.rn1) ++pn2;
   if (ph > 0 && r < L.rh0) --ph2;
   else if (ph < nr - 2 && r >= L.rh1) ++ph2;
-  double rn0 = L.rn0, irn = L.irn, rh0 = L.rh0, irh = L.irh;
   if (pn2 != pn || ph2 != ph) {
-    pn = pn2;
-    ph = ph2;
-    corner_loads(F, nrn, nrh, pn, ph, L.qn, L.qh, L.c);
-    rn0 = g.rn[pn];
-    irn = g.idrn[pn];
-    rh0 = g.rh[ph];
-    irh = g.idrh[ph];
+    L.pn = pn2;
+    L.ph = ph2;
+    corner_loads(F, nrn, nrh, pn2, ph2, L.qn, L.qh, L.c);
+    L.rn0 = g.rn[pn2];
+    L.rn1 = g.rn[pn2 + 1];
+    L.irn = g.idrn[pn2];
+    L.rh0 = g.rh[ph2];
+    L.rh1 = g.rh[ph2 + 1];
+    L.irh = g.idrh[ph2];
   }
+}
+
+// the interpolation itself, from settled loads
+__device__ __forceinline__ void gather_interp(const GridView& g, double r, double th,
+                                              double isg, const GatherLoads& L, double* D,
+                                              double* B) {
   const float2* c = L.c;
-  const double frn = clamp01((r - rn0) * irn), frh = clamp01((r - rh0) * irh);
+  const double frn = clamp01((r - L.rn0) * L.irn), frh = clamp01((r - L.rh0) * L.irh);
   const double ftn = clamp01((th - theta_node(g, L.qn)) * g.inv_dth);
   const double fth = clamp01((th - theta_half(g, L.qh)) * g.inv_dth);
   D[0] = lerp2(c[0], c[1], frh, ftn) * isg;
@@ -344,6 +354,31 @@ __device__ __forceinline__ void gather_finish(const GridView& g, const FieldView
   B[0] = lerp2(c[6], c[7], frn, fth) * isg;
   B[1] = lerp2(c[8], c[9], frh, ftn) * isg;
   B[2] = lerp2(c[10], c[11], frh, fth) * isg;
+}
+
+__device__ __forceinline__ void gather_finish(const GridView& g, const FieldView& F,
+                                              double r, double th, double isg,
+                                              GatherLoads& L, double* D, double* B) {
+  gather_settle(g, F, r, L);
+  gather_interp(g, r, th, isg, L, D, B);
+}
+
+// True when (r, th) lies in the cells whose corners L holds (L.pn < 0: none
+// yet), i.e. when a full gather would find exactly these cells: each cell is
+// the unique one with x_lo <= v < x_hi, open towards the clamped edges.
+// Arithmetic only; lets an iteration whose point stays in its cells reuse
+// the corners it loaded.
+__device__ __forceinline__ bool gather_hit(const GridView& g, double r, double th,
+                                           const GatherLoads& L) {
+  const int nr = g.nr, nth = g.nth;
+  if (L.pn < 0) return false;
+  const bool tn_ok = (L.qn == 0 || th >= theta_node(g, L.qn)) &&
+                     (L.qn == nth - 1 || th < theta_node(g, L.qn + 1));
+  int qh = th >= theta_half(g, L.qn) ? L.qn : L.qn - 1;
+  qh = qh < 0 ? 0 : (qh > nth - 2 ? nth - 2 : qh);
+  const bool rn_ok = (L.pn == 0 || r >= L.rn0) && (L.pn == nr - 1 || r < L.rn1);
+  const bool rh_ok = (L.ph == 0 || r >= L.rh0) && (L.ph == nr - 2 || r < L.rh1);
+  return tn_ok && qh == L.qh && rn_ok && rh_ok;
 }
 
 __device__ __forceinline__ void gather(const GridView& g, const FieldView& F,

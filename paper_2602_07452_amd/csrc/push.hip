@@ -85,10 +85,15 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
 // SPLIT: issue the field loads first and compute the gravity terms while
 // they are in flight (more registers: pays where occupancy is already two
 // waves per SIMD, the implicit pass)
-template <bool GRID, bool SPLIT = false>
+// CACHE: gc holds the corners of the cells of an earlier evaluation and is
+// reused without memory traffic while the point stays in those cells (the
+// implicit iterates, whose points move by far less than a cell); a miss
+// loads the new cells into gc, issued before the gravity terms.
+template <bool GRID, bool SPLIT = false, bool CACHE = false>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      const double* z, double s, double c, double* f,
-                                     double* pw, double* e = nullptr) {
+                                     double* pw, double* e = nullptr,
+                                     GatherLoads* gc = nullptr) {
   const double a = A.a, a2 = a * a, r = z[0], ur = z[3], ut = z[4], up = z[5];
   const double s2 = s * s, sc = s * c;
   // one inverse square root y = (rho2 S)^(-1/2) gives alpha = sqrt(rho2 / S)
@@ -102,11 +107,16 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
   const bool charged = GRID && qm != 0.0;
   GatherLoads gl;
+  bool hit = false;
   if (charged) {
-    if constexpr (SPLIT)
+    if constexpr (CACHE) {
+      hit = gather_hit(A.g, r, z[1], *gc);
+      if (!hit) gather_issue(A.g, A.f, r, z[1], *gc);
+    } else if constexpr (SPLIT) {
       gather_issue(A.g, A.f, r, z[1], gl);
-    else
+    } else {
       gather(A.g, A.f, r, z[1], isg, D, B);
+    }
   }
   // contravariant momentum gamma^ij u_j and the Lorentz factor
   const double irp = a * irho2;
@@ -129,7 +139,12 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double dxt = 4.0 * r * a2 * sc * i4;                      // d_theta xi
   const double gr = dxr * Cq + aiG * r * i4 * Aq;
   const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
-  if constexpr (SPLIT) {
+  if constexpr (CACHE) {
+    if (charged) {
+      if (!hit) gather_settle(A.g, A.f, r, *gc);
+      gather_interp(A.g, r, z[1], isg, *gc, D, B);
+    }
+  } else if constexpr (SPLIT) {
     if (charged) gather_finish(A.g, A.f, r, z[1], isg, gl, D, B);
   }
   if (qm != 0.0) {
@@ -163,14 +178,18 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
 // RK4; *e0 = energy e at z (from the first stage)
 // classical RK4 with the fields re-gathered at every stage; s0, c0 (out):
 // sin, cos of z[1], from which the stage angles are reached by short series
-template <bool GRID>
+// CACHE: the stages reuse the field corners of the previous stage's cells
+// while they stay in them
+template <bool GRID, bool CACHE = false>
 __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
                                     const double* z, double* out, double* Wq,
                                     double* e0, double* s0, double* c0) {
   const double hdt = 0.5 * dt;
   double k[6], acc[6], y[6], p, pacc, s, c;
+  GatherLoads gc;
+  gc.pn = -1;
   fsincos(z[1], s0, c0);
-  eval<GRID>(A, qm, z, *s0, *c0, k, &p, e0);
+  eval<GRID, false, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] = k[i];
@@ -178,7 +197,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc = p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID>(A, qm, y, s, c, k, &p);
+  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
@@ -186,7 +205,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc += 2.0 * p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID>(A, qm, y, s, c, k, &p);
+  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
@@ -194,7 +213,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc += 2.0 * p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID>(A, qm, y, s, c, k, &p);
+  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
   const double c6 = dt / 6.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) out[i] = z[i] + c6 * (acc[i] + k[i]);
@@ -212,17 +231,21 @@ __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
   return m <= tol;
 }
 
-// implicit midpoint rule by fixed-point iteration; zk: guess in, result out
+// implicit midpoint rule by fixed-point iteration; zk: guess in, result out.
+// The field corners of the midpoint's cells are kept across iterations and
+// reloaded only when the midpoint leaves those cells.
 template <bool GRID, bool SPLIT = false>
 __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, double s0,
                    double c0, double* zk, double* Wq) {
   double p = 0.0;
+  GatherLoads gc;
+  gc.pn = -1;
   for (int k = 1; k <= A.kmax; ++k) {
     double zm[6], f[6], zn[6], sm, cm;
 #pragma unroll
     for (int i = 0; i < 6; ++i) zm[i] = 0.5 * (z[i] + zk[i]);
     sincos_near(zm[1], z[1], s0, c0, &sm, &cm);
-    eval<GRID, SPLIT>(A, qm, zm, sm, cm, f, &p);
+    eval<GRID, SPLIT, GRID>(A, qm, zm, sm, cm, f, &p, nullptr, &gc);
 #pragma unroll
     for (int i = 0; i < 6; ++i) zn[i] = z[i] + dt * f[i];
     bool c = small_change(zn, zk, A.tol);
@@ -250,12 +273,14 @@ template <bool GRID>
 __device__ int imr_newton(const PushArgs& A, double dt, double qm, const double* z,
                           double s0, double c0, double* zk, double* Wq) {
   double p = 0.0;
+  GatherLoads gc;  // corners of the midpoint's cells, as in imr
+  gc.pn = -1;
   for (int k = 1; k <= A.kmax; ++k) {
     double m[6], f0[6], J[6][7] = {}, sm, cm;
 #pragma unroll
     for (int i = 0; i < 6; ++i) m[i] = 0.5 * (z[i] + zk[i]);
     sincos_near(m[1], z[1], s0, c0, &sm, &cm);
-    eval<GRID>(A, qm, m, sm, cm, f0, &p);
+    eval<GRID, false, GRID>(A, qm, m, sm, cm, f0, &p, nullptr, &gc);
 #pragma unroll 1
     for (int j = 0; j < 6; ++j) {
       double mj[6], fj[6], pj, sj, cj, mv = m[0];
@@ -267,7 +292,7 @@ __device__ int imr_newton(const PushArgs& A, double dt, double qm, const double*
 #pragma unroll
       for (int i = 0; i < 6; ++i) mj[i] = i == j ? sv : m[i];
       sincos_near(mj[1], z[1], s0, c0, &sj, &cj);
-      eval<GRID>(A, qm, mj, sj, cj, fj, &pj);
+      eval<GRID, false, GRID>(A, qm, mj, sj, cj, fj, &pj, nullptr, &gc);
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const double v = (i == j ? 1.0 : 0.0) - 0.5 * dt * (fj[i] - f0[i]) / h;
@@ -492,7 +517,7 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
   P.uph[k] = out[5];
   P.herr[k] = herr;
   P.flags[k] = fl;
-  P.iters[k] = (uint8_t)iters;
+  P.iters[k] = (uint8_t)(iters < 255 ? iters : 255);  // a restart can take 2 kmax
   if (fl & F_ALIVE) {
     atomicAdd(&ls.alive, 1u);
     atomicAdd(&ls.herr_hist[herr_bin(herr)], 1u);
@@ -529,7 +554,7 @@ __device__ __forceinline__ void load_z(const ParticleView& P, long k,
 }
 
 // ------------------------------------------------------- explicit pass
-template <bool GRID, bool EVOLVE, int WPS>
+template <bool GRID, bool EVOLVE, int WPS, bool CACHE = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS)))
 void k_push_explicit(PushArgs A) {
   __shared__ LocalStats ls;
@@ -571,7 +596,7 @@ void k_push_explicit(PushArgs A) {
       for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
     } else {
       double Wq, e0, s0, c0;
-      rk4<GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0);
+      rk4<GRID, CACHE && GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0);
       double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
@@ -670,8 +695,12 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         it = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
       else
         it = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq);
-      if (it < 0 && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
-        // no convergence from the learned guess: restart from z^n
+      bool finite = true;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) finite = finite && isfinite(zk[i]);
+      if ((it < 0 || !finite) && A.guess == GRPIC_GUESS_MLP && !A.col.T) {
+        // no convergence from the learned guess (a non-finite iterate passes
+        // the stopping test, whose maximum skips NaN): restart from z^n
 #pragma unroll
         for (int i = 0; i < 6; ++i) zk[i] = z[i];
         int it2;
