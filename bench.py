@@ -412,12 +412,14 @@ def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
            "train": {"samples": samples, "epochs": epochs, "batch": 4096,
                      "loss_first_epoch": float(loss[0]), "loss_last_epoch": float(loss[-1]),
                      "seconds": t_train}}
-    for name, guess in (("plain", G.GUESS_PLAIN), ("learned", G.GUESS_MLP)):
+    def run(guess, tol=None, theta=None):
         c = cfg(guess)
+        if tol is not None:
+            c.tol = tol
         with G.Context(c) as ctx:
             init(ctx, c, SEED + 9)
-            if guess == G.GUESS_MLP:
-                ctx.mlp_set(*net)
+            if theta is not None:
+                ctx.mlp_set(*theta)
             ctx.step(2)
             ctx.sync()
             d0 = ctx.diagnostics()
@@ -426,12 +428,45 @@ def learned_vs_plain(G, steps, n=1 << 20, dt=0.01, collect_steps=4, epochs=20):
             ctx.sync()
             t1 = time.perf_counter()
             d1 = ctx.diagnostics()
+            # kernel times per step, over three more steps
+            ctx.enable_timing(True)
+            ctx.reset_timings()
+            ctx.step(3)
+            ctx.sync()
+            tim = ctx.timings()
         h = d1["iter_hist"] - d0["iter_hist"]
-        out[name] = {"value": n * steps / (t1 - t0), "unit": "particle-steps/s",
-                     "mean_iterations": float(h @ np.arange(len(h)) / max(h.sum(), 1)),
-                     "h_error": herr_percentiles(d1["herr_hist"]),
-                     "not_converged": int(d1["noconv"] - d0["noconv"])}
+        return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s",
+                "mean_iterations": float(h @ np.arange(len(h)) / max(h.sum(), 1)),
+                "h_error": herr_percentiles(d1["herr_hist"]),
+                "not_converged": int(d1["noconv"] - d0["noconv"]),
+                "implicit_ms_per_step": tim.get("implicit", (0.0, 0))[0] / 3,
+                "guess_ms_per_step": tim.get("guess", (0.0, 0))[0] / 3}
+
+    out["plain"] = run(G.GUESS_PLAIN)
+    out["learned"] = run(G.GUESS_MLP, theta=net)
     out["speedup"] = out["learned"]["value"] / out["plain"]["value"]
+    # What any guess of BF16 accuracy could gain here.  The Picard iteration
+    # contracts its error by rho per iteration: rho from the mean counts at
+    # two stopping tolerances (1e-13 and 1e-10, three decades apart).  A
+    # guess correcting the Euler step to the 2^-9 relative accuracy of BF16
+    # starts log10(512) / log10(1/rho) iterations and one evaluation (the
+    # Euler base) ahead of z^n; it costs the base's evaluation plus the
+    # network.  c_iter: implicit-pass time per particle-iteration of the
+    # plain run; the network's cost is the guess kernel's time per particle
+    # in those units (it includes the base's evaluation and the features).
+    loose = run(G.GUESS_PLAIN, tol=1e-10)
+    k13, k10 = out["plain"]["mean_iterations"], loose["mean_iterations"]
+    rho = 10.0 ** (-3.0 / max(k13 - k10, 1e-9))
+    floor_its = max(1.0, k13 - 1.0 - np.log10(512.0) / np.log10(1.0 / rho))
+    c_iter = out["plain"]["implicit_ms_per_step"] / max(k13, 1e-9)
+    net_cost = out["learned"]["guess_ms_per_step"] / c_iter if c_iter > 0 else None
+    out["bound"] = {
+        "rho": rho, "mean_iterations_tol_1e-10": k10,
+        "iterations_floor_bf16_guess": floor_its,
+        "speedup_max_free_network": k13 / (1.0 + floor_its),
+        "network_cost_iterations": net_cost,
+        "speedup_max_with_measured_network": (k13 / (net_cost + floor_its)
+                                              if net_cost is not None else None)}
     return out
 
 
@@ -626,7 +661,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain guess comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
-    ap.add_argument("--learned-dt", type=float, nargs="+", default=[0.01, 0.1],
+    ap.add_argument("--learned-dt", type=float, nargs="+", default=[0.01, 0.03, 0.1],
                     help="time steps of the learned-vs-plain comparison on the charged "
                          "test-particle workload")
     ap.add_argument("--no-plain", action="store_true",
