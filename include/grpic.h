@@ -245,7 +245,9 @@ int grpic_load_particles(grpic_ctx *ctx, long n, const double *r,
                          const double *qm, const double *w, const double *H0,
                          const double *herr);
 /* Copy the particles back in id order.  Any pointer may be NULL.  flags
- * and iters describe the last step.                                       */
+ * and iters describe the last step: iters is the implicit iteration count
+ * (0 for an explicit step); after a restart from z^n (learned guess) it is
+ * kmax plus the restart's count, capped at 255.                           */
 int grpic_get_particles(grpic_ctx *ctx, long n, double *r, double *th,
                         double *ph, double *ur, double *uth, double *uph,
                         double *qm, double *w, double *H0, double *herr,
@@ -302,7 +304,15 @@ int grpic_get_state(grpic_ctx *ctx, void *host, size_t bytes);
 int grpic_set_state(grpic_ctx *ctx, const void *host, size_t bytes);
 
 /* ---- stepping ---------------------------------------------------------- */
-/* Advance nsteps steps, asynchronously on the context's stream.           */
+/* Advance nsteps steps, asynchronously on the context's stream.  One step
+ * is the cycle of Sec. 2.1: with field_mode EVOLVE the Maxwell sub-steps
+ * 1-4, the push of sub-step 5 (gather at every stage, RK4 of Sec. 2.2.1,
+ * the hybrid switch of Sec. 3.1.2 and the implicit redo of Sec. 2.2.2 or
+ * 2.2.3, particle boundaries of Sec. 2.5), the deposit of sub-step 6
+ * (Sec. 2.3) and sub-steps 7-10; without a grid or with static fields the
+ * push alone (no particles: the fields alone).  Errors: GRPIC_E_INVALID
+ * for nsteps < 0, GRPIC_E_STATE with guess MLP and no network set (and no
+ * sample collection running), GRPIC_E_HIP.                               */
 int grpic_step(grpic_ctx *ctx, int nsteps);
 /* Capture one step in a hipGraph and replay it for grpic_step (1) or go
  * back to eager launches (0).                                             */
@@ -326,6 +336,9 @@ typedef struct grpic_diag {
   long nonfinite;        /* particles removed for a non-finite state
                             (cumulative, also counted in removed)          */
 } grpic_diag;
+/* The counters above (synchronises the stream).  The energy violation is
+ * the hybrid switch quantity of Sec. 3.1.2 (|H - H_0| / |H_0| for neutral
+ * particles, the per-step energy-budget residual for charged ones).        */
 int grpic_get_diagnostics(grpic_ctx *ctx, grpic_diag *out);
 /* Grid diagnostics on the integer chain: max |Gauss residual| over interior
  * nodes (eq. m1, densitized), max |div B| (eq. m2) and the Poynting
@@ -394,7 +407,7 @@ int grpic_enable_timing(grpic_ctx *ctx, int enable);
 int grpic_get_timings(grpic_ctx *ctx, double *ms, long *count);
 int grpic_reset_timings(grpic_ctx *ctx);
 
-/* ---- autotuner (project extension) ------------------------------------
+/* ---- autotuner (project extension, not in the paper) -------------------
  * Times the step under candidate launch settings and keeps the fastest, by
  * coordinate search: sort tile (tile_r x tile_th in {16x16, 32x16, 32x32,
  * 64x16, 64x32}; grid contexts), implicit-pass waves per CU {4, 8, 16, 32}

@@ -213,6 +213,110 @@ __device__ __forceinline__ void forward(const WeightsLds& W, const bf16* X,
     for (int v = 0; v < 4; ++v) y[mt][0][v] += W.b3[i];
 }
 
+// ------------------------------------------- inference (guess, checks)
+// GELU by the tanh form x sigma(2 sqrt(2/pi) (x + 0.044715 x^3)) (Hendrycks
+// & Gimpel), at most 4.7e-4 from x Phi(x) (at x = 2.7): below the BF16
+// rounding of the activations that follows.  Two hardware estimates (exp2,
+// reciprocal) and five FP32 operations.
+__device__ __forceinline__ float gelu_fast(float x) {
+  constexpr float k0 = -2.0f * 0.79788456080286536f * 1.4426950408889634f;
+  constexpr float k1 = k0 * 0.044715f;
+  const float t = x * __builtin_fmaf(k1, x * x, k0);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+// four FP32 values as one BF16 operand (hardware round to nearest even)
+__device__ __forceinline__ s4 pack_bf16(float a, float b, float c, float d) {
+  const bf2v lo = __builtin_convertvector((f2v){a, b}, bf2v);
+  const bf2v hi = __builtin_convertvector((f2v){c, d}, bf2v);
+  return __builtin_bit_cast(s4, (u2v){__builtin_bit_cast(unsigned, lo),
+                                       __builtin_bit_cast(unsigned, hi)});
+}
+
+// Forward pass of 64 rows on one wavefront, transposed: each layer computes
+// H^T = W H_prev^T (hidden units x rows), so the accumulator a lane holds
+// after one layer (rows 4 (l/16) + v of a 16-unit block, column l % 16) is
+// exactly its B operand of the next layer's 16x16x16 product; activations
+// never leave the registers.  X: [64][LDX] BF16 inputs in LDS (row = one
+// network input row); Y: [64][LDY] FP32 outputs in LDS (columns 0..5).
+__device__ __forceinline__ void forward_chained(const WeightsLds& W, const bf16* X, float* Y) {
+  const int l = threadIdx.x & 63, i = l & 15, g = (l >> 4) * 4;
+  s4 hb[4][4];  // [unit block][row block] BF16 activations, B operands
+  {
+    f4 acc[4][4];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      const s4 b = ld4(X + (pb * 16 + i) * LDX + g);
+#pragma unroll
+      for (int ho = 0; ho < 4; ++ho) {
+        const s4 a = ld4(W.W1 + (ho * 16 + i) * LDX + g);
+        acc[ho][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, f4{0.f, 0.f, 0.f, 0.f},
+                                                               0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int ho = 0; ho < 4; ++ho) {
+      const f4 bias = *reinterpret_cast<const f4*>(W.b1 + ho * 16 + g);
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb)
+        hb[ho][pb] = pack_bf16(gelu_fast(acc[ho][pb][0] + bias[0]),
+                               gelu_fast(acc[ho][pb][1] + bias[1]),
+                               gelu_fast(acc[ho][pb][2] + bias[2]),
+                               gelu_fast(acc[ho][pb][3] + bias[3]));
+    }
+  }
+  {
+    f4 acc[4][4];
+#pragma unroll
+    for (int ho = 0; ho < 4; ++ho)
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb) acc[ho][pb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int hi = 0; hi < 4; ++hi)
+#pragma unroll
+      for (int ho = 0; ho < 4; ++ho) {
+        const s4 a = ld4(W.W2 + (ho * 16 + i) * LDW + hi * 16 + g);
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+          acc[ho][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, hb[hi][pb], acc[ho][pb],
+                                                                 0, 0, 0);
+      }
+#pragma unroll
+    for (int ho = 0; ho < 4; ++ho) {
+      const f4 bias = *reinterpret_cast<const f4*>(W.b2 + ho * 16 + g);
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb)
+        hb[ho][pb] = pack_bf16(gelu_fast(acc[ho][pb][0] + bias[0]),
+                               gelu_fast(acc[ho][pb][1] + bias[1]),
+                               gelu_fast(acc[ho][pb][2] + bias[2]),
+                               gelu_fast(acc[ho][pb][3] + bias[3]));
+    }
+  }
+  f4 y[4];
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb) y[pb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int hi = 0; hi < 4; ++hi) {
+    const s4 a = ld4(W.W3 + i * LDW + hi * 16 + g);
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+      y[pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, hb[hi][pb], y[pb], 0, 0, 0);
+  }
+  // y[pb][v] = output g + v of row pb * 16 + i (outputs 0..5 in lanes 0..31)
+  if (g < 8) {
+    const f4 bias = *reinterpret_cast<const f4*>(W.b3 + g);
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (g + v < NO) Y[(pb * 16 + i) * LDY + g + v] = y[pb][v] + bias[v];
+  }
+}
+
 // ------------------------------------------------------------ guess kernel
 struct GuessArgs {
   GridView g;
@@ -241,7 +345,6 @@ __global__ __launch_bounds__(64 * kGuessWaves) void k_mlp_guess(GuessArgs A) {
   __shared__ float nrm[NNORM];
   __shared__ unsigned pref[kQueueSegs + 1];
   __shared__ __attribute__((aligned(16))) bf16 Xs[kGuessWaves][64 * LDX];
-  __shared__ __attribute__((aligned(16))) bf16 Hs[kGuessWaves][64 * LDW];
   __shared__ float Ys[kGuessWaves][64 * LDY];
   if (A.use_net) stage_weights(A.theta, W);
   for (int t = threadIdx.x; t < NNORM; t += blockDim.x) nrm[t] = A.use_net ? A.norm[t] : 0.f;
@@ -250,7 +353,6 @@ __global__ __launch_bounds__(64 * kGuessWaves) void k_mlp_guess(GuessArgs A) {
   const ParticleView& P = A.p;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   bf16* xs = Xs[w];
-  bf16* hs = Hs[w];
   float* ys = Ys[w];
   for (;;) {
     unsigned v0 = 0;
@@ -299,17 +401,14 @@ __global__ __launch_bounds__(64 * kGuessWaves) void k_mlp_guess(GuessArgs A) {
       x[13] = (float)m.betar;
     }
     if (A.use_net) {
+      // this lane's normalised features as row l of the input tile
+      auto feat = [&](int f) { return (act && f < NI) ? (x[f] - nrm[f]) * nrm[NI + f] : 0.f; };
 #pragma unroll
-      for (int i = 0; i < 16; ++i)
-        xs[l * LDX + i] = (act && i < NI) ? to_bf16((x[i] - nrm[i]) * nrm[NI + i]) : (bf16)0;
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<s4*>(xs + l * LDX + 4 * q) =
+            pack_bf16(feat(4 * q), feat(4 * q + 1), feat(4 * q + 2), feat(4 * q + 3));
       wave_sync();
-      f4 y[4][1];
-      forward(W, xs, hs, hs, y);
-      const int i = l & 15, g = (l >> 4) * 4;
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int vv = 0; vv < 4; ++vv) ys[(mt * 16 + g + vv) * LDY + i] = y[mt][0][vv];
+      forward_chained(W, xs, ys);
       wave_sync();
       if (act) {
 #pragma unroll
@@ -556,23 +655,22 @@ __global__ __launch_bounds__(64) void k_mlp_forward_rows(const float* theta, con
                                                          long n, float* Y) {
   __shared__ WeightsLds W;
   __shared__ __attribute__((aligned(16))) bf16 Xs[64 * LDX];
-  __shared__ __attribute__((aligned(16))) bf16 Hs[64 * LDW];
+  __shared__ float Ys[64 * LDY];
   stage_weights(theta, W);
-  const int l = threadIdx.x, i = l & 15, g = (l >> 4) * 4;
+  const int l = threadIdx.x;
   const long r0 = (long)blockIdx.x * 64;
+  auto feat = [&](int c) { return (r0 + l < n && c < NI) ? X[(r0 + l) * NI + c] : 0.f; };
 #pragma unroll
-  for (int c = 0; c < 16; ++c)
-    Xs[l * LDX + c] = (r0 + l < n && c < NI) ? to_bf16(X[(r0 + l) * NI + c]) : (bf16)0;
+  for (int q = 0; q < 4; ++q)
+    *reinterpret_cast<s4*>(Xs + l * LDX + 4 * q) =
+        pack_bf16(feat(4 * q), feat(4 * q + 1), feat(4 * q + 2), feat(4 * q + 3));
   __syncthreads();
-  f4 y[4][1];
-  forward(W, Xs, Hs, Hs, y);
+  forward_chained(W, Xs, Ys);
+  __syncthreads();
+  if (r0 + l < n) {
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      long r = r0 + mt * 16 + g + v;
-      if (i < NO && r < n) Y[r * NO + i] = y[mt][0][v];
-    }
+    for (int o = 0; o < NO; ++o) Y[(r0 + l) * NO + o] = Ys[l * LDY + o];
+  }
 }
 
 // feature / target moments: per block partial sums of x and x^2 (20 columns)
