@@ -124,26 +124,54 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
   dep_weights_at(g, r, th, st, ct, g.rn[p], g.rn[p + 1], g.stn[q], g.ctn[q], q, W);
 }
 
-// node cell (p, q) of (r, th) and its weights, with the node values loaded in
-// one memory round trip (the FP32 radial estimate is checked against them)
+// A node column known from a nearby gather: rn[pn] = rn0, rn[pn + 1] = rn1
+// (pn < 0: none).
+struct ColumnHint {
+  int pn;
+  double rn0, rn1;
+};
+
+// node cell (p, q) of (r, th) and its weights.  hint: the node column of a
+// nearby gather (the last RK4 stage); when r lies in it the radii come from
+// it, else the node values are loaded in one memory round trip (the FP32
+// radial estimate is checked against them).
+// The sin and cos of the cell's lower node angle follow from those of th by
+// the short series of sincos_near when the two are close, else from the
+// node tables.
 __device__ __forceinline__ void cell_and_weights(const GridView& g, double r, double th,
                                                  double st, double ct, int& p, int& q,
-                                                 double* W) {
+                                                 double* W,
+                                                 ColumnHint hint = ColumnHint{-1, 0.0, 0.0}) {
   const int nr = g.nr;
   q = theta_cell<false>(g, th, (th - g.th0) * g.inv_dth, g.nth + 1);
-  int p0 = (int)floorf(radial_coord(g, r));
-  p0 = p0 < 0 ? 0 : (p0 > nr - 1 ? nr - 1 : p0);
-  double r0 = g.rn[p0], r1 = g.rn[p0 + 1];
-  const double sq = g.stn[q], cq = g.ctn[q];
-  p = p0;
-  if (p0 > 0 && r < r0) {
-    p = p0 - 1;
-    r1 = r0;
-    r0 = g.rn[p];
-  } else if (p0 < nr - 1 && r >= r1) {
-    p = p0 + 1;
-    r0 = r1;
-    r1 = g.rn[p + 1];
+  double r0, r1;
+  if (hint.pn >= 0 && (hint.pn == 0 || r >= hint.rn0) && (hint.pn == nr - 1 || r < hint.rn1)) {
+    p = hint.pn;
+    r0 = hint.rn0;
+    r1 = hint.rn1;
+  } else {
+    int p0 = (int)floorf(radial_coord(g, r));
+    p0 = p0 < 0 ? 0 : (p0 > nr - 1 ? nr - 1 : p0);
+    r0 = g.rn[p0];
+    r1 = g.rn[p0 + 1];
+    p = p0;
+    if (p0 > 0 && r < r0) {
+      p = p0 - 1;
+      r1 = r0;
+      r0 = g.rn[p];
+    } else if (p0 < nr - 1 && r >= r1) {
+      p = p0 + 1;
+      r0 = r1;
+      r1 = g.rn[p + 1];
+    }
+  }
+  const double tq = theta_node(g, q);
+  double sq, cq;
+  if (fabs(tq - th) <= 0.01) {
+    sincos_near(tq, th, st, ct, &sq, &cq);
+  } else {
+    sq = g.stn[q];
+    cq = g.ctn[q];
   }
   dep_weights_at(g, r, th, st, ct, r0, r1, sq, cq, q, W);
 }

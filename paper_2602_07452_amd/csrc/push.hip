@@ -183,13 +183,13 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
 // so three of the four stage gathers mostly need no memory round trip; the
 // cached corners raise the explicit push from 154 to 184 VGPRs, three to
 // two waves per SIMD, and still take 3.5 % off its time on 2^27 particles)
+// gc (out): the gather cells of the last stage (pn = -1 without the cache)
 template <bool GRID, bool CACHE = false>
 __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
                                     const double* z, double* out, double* Wq,
-                                    double* e0, double* s0, double* c0) {
+                                    double* e0, double* s0, double* c0, GatherLoads& gc) {
   const double hdt = 0.5 * dt;
   double k[6], acc[6], y[6], p, pacc, s, c;
-  GatherLoads gc;
   gc.pn = -1;
   fsincos(z[1], s0, c0);
   eval<GRID, false, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc);
@@ -461,12 +461,16 @@ __device__ int ham_dg(const PushArgs& A, double dt, const double* z, double* zk)
 // neutral: |e - H0| / |H0|; charged: |e' - e - W| / |e| (W: the scheme's
 // quadrature of (q/m) E_i dx^i/dt)
 // zn: the new state; s0, c0: sin, cos of the old angle z0
+// (*sn, *cn: sin, cos of zn[1], for finalize)
 __device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
                                                double H0, double e0,
                                                const double* zn, double Wq,
-                                               double z0, double s0, double c0) {
+                                               double z0, double s0, double c0,
+                                               double* sn, double* cn) {
   double s, c;
   sincos_near(zn[1], z0, s0, c0, &s, &c);
+  *sn = s;
+  *cn = c;
   double e1 = energy_sc(A.a, zn, s, c);
   if (qm == 0.0) return fabs(e1 - H0) / fabs(H0);
   return fabs(e1 - e0 - Wq) / fabs(e0);
@@ -485,9 +489,11 @@ __device__ __forceinline__ int herr_bin(double v) {
 // deposit) store the old position and the weights of the new one
 // s0, c0: sin, cos of z[1]
 template <bool EVOLVE>
+// sn, cn: sin, cos of out[1] as pushed; hint: the last stage's node column
 __device__ void finalize(const PushArgs& A, long k, const double* z,
                          double* out, double herr, int iters, uint8_t fl,
-                         LocalStats& ls, double s0, double c0) {
+                         LocalStats& ls, double s0, double c0, double sn, double cn,
+                         ColumnHint hint) {
   const ParticleView& P = A.p;
   bool finite = true;
 #pragma unroll
@@ -512,6 +518,7 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
       atomicAdd(&ls.reflected, 1u);
     }
   }
+  const bool moved = (fl & F_REFLECTED) != 0;
   P.r[k] = out[0];
   P.th[k] = out[1];
   P.ph[k] = out[2];
@@ -536,9 +543,9 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
     P.dphi[k] = out[2] - z[2];
     if (fl & F_ALIVE) {
       int p, q;
-      double W[4], st, ct;
-      sincos_near(out[1], z[1], s0, c0, &st, &ct);
-      cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W);
+      double W[4], st = sn, ct = cn;
+      if (moved) sincos_near(out[1], z[1], s0, c0, &st, &ct);
+      cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W, hint);
 #pragma unroll
       for (int c = 1; c < 4; ++c) P.Wn[c][k] = W[c];
       P.celln[k] = q * A.g.nr + p;
@@ -598,9 +605,10 @@ void k_push_explicit(PushArgs A) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) trial[i] = z[i];  // no RK4 trial: start at z^n
     } else {
-      double Wq, e0, s0, c0;
-      rk4<GRID, CACHE && GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0);
-      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0);
+      double Wq, e0, s0, c0, sn, cn;
+      GatherLoads gc;
+      rk4<GRID, CACHE && GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0, gc);
+      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0, &sn, &cn);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
         accept = v < A.thr;
@@ -609,7 +617,8 @@ void k_push_explicit(PushArgs A) {
         accept = (v - prev) / (dt * fmax(prev, 0x1p-52)) < A.thr;
       }
       if (accept) {
-        finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0);
+        finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0, sn, cn,
+                         ColumnHint{gc.pn, gc.rn0, gc.rn1});
         if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
       } else {
         enq = true;
@@ -727,8 +736,10 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         }
       }
       double e0 = qm != 0.0 ? energy_sc(A.a, z, s0, c0) : 0.0;
-      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0);
-      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0);
+      double sn, cn;
+      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0, &sn, &cn);
+      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0, sn, cn,
+                       ColumnHint{-1, 0.0, 0.0});
       if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
     }
   }
