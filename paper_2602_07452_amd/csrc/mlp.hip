@@ -939,9 +939,9 @@ void launch_guess(grpic_ctx* c) {
   A.rows = coll ? s->rows : nullptr;
   A.cap = coll ? s->cap : 0;
   long need = (c->n + 64 * kGuessWaves - 1) / (64 * kGuessWaves);
-  // three blocks per CU (as many as its 43 KB of LDS and 149 VGPRs allow):
-  // the features' gather waits on memory, more waves hide it
-  long blocks = std::min<long>(3L * c->num_cus, std::max<long>(need, 1));
+  // two blocks per CU: with 149 VGPRs and 96 accumulation registers the
+  // kernel holds two waves per SIMD
+  long blocks = std::min<long>(2L * c->num_cus, std::max<long>(need, 1));
   hipEvent_t ev;
   time_begin(c, GRPIC_K_GUESS, &ev);
   hipLaunchKernelGGL(k_mlp_guess, dim3((unsigned)blocks), dim3(64 * kGuessWaves), 0,
