@@ -237,9 +237,10 @@ __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
 // implicit midpoint rule by fixed-point iteration; zk: guess in, result out.
 // The field corners of the midpoint's cells are kept across iterations and
 // reloaded only when the midpoint leaves those cells.
+// col (out): the node column of the last midpoint's gather (pn = -1: none)
 template <bool GRID, bool SPLIT = false>
 __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, double s0,
-                   double c0, double* zk, double* Wq) {
+                   double c0, double* zk, double* Wq, ColumnHint* col) {
   double p = 0.0;
   GatherLoads gc;
   gc.pn = -1;
@@ -256,10 +257,12 @@ __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, dou
     for (int i = 0; i < 6; ++i) zk[i] = zn[i];
     if (c) {
       *Wq = dt * p;
+      *col = ColumnHint{gc.pn, gc.rn0, gc.rn1};
       return k;
     }
   }
   *Wq = dt * p;
+  *col = ColumnHint{gc.pn, gc.rn0, gc.rn1};
   return -A.kmax;
 }
 
@@ -701,12 +704,13 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         }
       }
       double Wq = 0.0, s0, c0;
+      ColumnHint col{-1, 0.0, 0.0};  // Picard: the last midpoint's node column
       fsincos(z[1], &s0, &c0);
       int it;
       if constexpr (NEWTON)
         it = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
       else
-        it = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq);
+        it = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq, &col);
       bool finite = true;
 #pragma unroll
       for (int i = 0; i < 6; ++i) finite = finite && isfinite(zk[i]);
@@ -719,7 +723,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         if constexpr (NEWTON)
           it2 = ham ? ham_dg(A, dt, z, zk) : imr_newton<GRID>(A, dt, qm, z, s0, c0, zk, &Wq);
         else
-          it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq);
+          it2 = ham ? ham_dg(A, dt, z, zk) : imr<GRID, EVOLVE>(A, dt, qm, z, s0, c0, zk, &Wq, &col);
         it = it2 < 0 ? it2 - A.kmax : it2 + A.kmax;
       }
       uint8_t fl = F_ALIVE | F_IMPLICIT;
@@ -738,8 +742,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       double e0 = qm != 0.0 ? energy_sc(A.a, z, s0, c0) : 0.0;
       double sn, cn;
       double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0, &sn, &cn);
-      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0, sn, cn,
-                       ColumnHint{-1, 0.0, 0.0});
+      finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0, sn, cn, col);
       if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
     }
   }
