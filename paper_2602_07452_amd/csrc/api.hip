@@ -486,7 +486,9 @@ void run_step(grpic_ctx* c) {
   if (c->cfg.inj_every > 0 && c->steps % c->cfg.inj_every == 0) inject_now(c);
   if (c->cfg.sort_every > 0 && c->cfg.field_mode != GRPIC_FIELDS_NONE &&
       c->steps % c->cfg.sort_every == 0)
-    launch_sort(c);  // swaps the buffer sets: the other cached graphs apply
+    // swaps the buffer sets (the other cached graphs apply); the full cycle
+    // keeps every particle's node cell, which gives its tile directly
+    launch_sort(c, c->cfg.field_mode == GRPIC_FIELDS_EVOLVE);
 }
 
 hipEvent_t take_event(grpic_ctx* c) {

@@ -205,7 +205,9 @@ long deposit_blocks(const grpic_ctx* c);
 void invalidate_deposit_plan(grpic_ctx* c);
 // measured FP64 FMA rate (TFLOP/s) and streaming copy rate (TB/s)
 void probe_peaks(grpic_ctx* c, double* fma_tflops, double* copy_tbs);
-void launch_sort(grpic_ctx* c);
+// from_cells: the tile keys come from the stored node cells of the current
+// positions (kept by every full-cycle step) instead of r and theta
+void launch_sort(grpic_ctx* c, bool from_cells = false);
 void launch_sample(grpic_ctx* c, const int* map, double* out, int* fl);
 void launch_field_diag(grpic_ctx* c, double* gauss_max, double* divb_max,
                        double* pbz);

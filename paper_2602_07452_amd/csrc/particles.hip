@@ -104,12 +104,19 @@ struct SortArgs {
   int tile_r, tile_th, ntr, ntiles;
   int* count;
   int* offset;
+  const int* cell;  // node cells of the current positions (nullptr: from r, theta)
 };
 
 __device__ __forceinline__ int tile_key(const SortArgs& A, long k) {
   if (!(A.p.flags[k] & GRPIC_FLAG_ALIVE)) return A.ntiles;
   int p, q;
-  node_cell(A.g, A.p.r[k], A.p.th[k], p, q);
+  if (A.cell) {
+    const unsigned c = (unsigned)A.cell[k];
+    q = (int)(c / (unsigned)A.g.nr);
+    p = (int)(c - (unsigned)q * (unsigned)A.g.nr);
+  } else {
+    node_cell(A.g, A.p.r[k], A.p.th[k], p, q);
+  }
   // serpentine order: odd tile rows run backwards in r, so consecutive
   // tiles are always neighbours
   int tq = q / A.tile_th, tp = p / A.tile_r;
@@ -178,26 +185,70 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
     hist[i] = 0;
   }
   __syncthreads();
+  // four particles per thread at a time, all their loads issued before the
+  // stores (one scattered particle at a time kept too few loads in flight)
   const ParticleView &S = A.p, &D = A.q;
-  for (long k = beg + threadIdx.x; k < end; k += blockDim.x) {
-    int key = tile_key(A, k);
-    long d = base[key] + atomicAdd(&hist[key], 1);
-    D.r[d] = S.r[k];
-    D.th[d] = S.th[k];
-    D.ph[d] = S.ph[k];
-    D.ur[d] = S.ur[k];
-    D.uth[d] = S.uth[k];
-    D.uph[d] = S.uph[k];
-    D.H0[d] = S.H0[k];
-    D.herr[d] = S.herr[k];
-    D.w[d] = S.w[k];
-    D.qm[d] = S.qm[k];
-    D.flags[d] = S.flags[k];
-    D.iters[d] = S.iters[k];
-    D.id[d] = S.id[k];
+  constexpr int U = 4;
+  for (long k0 = beg + threadIdx.x; k0 < end; k0 += U * (long)blockDim.x) {
+    long kk[U], d[U];
 #pragma unroll
-    for (int c = 1; c < 4; ++c) D.W[c][d] = S.W[c][k];
-    D.cell[d] = S.cell[k];
+    for (int u = 0; u < U; ++u) {
+      kk[u] = k0 + u * (long)blockDim.x;
+      d[u] = -1;
+      if (kk[u] < end) {
+        const int key = tile_key(A, kk[u]);
+        d[u] = base[key] + atomicAdd(&hist[key], 1);
+      }
+    }
+    double x[U][12];
+    int8_t qm[U];
+    uint8_t fl[U], it[U];
+    uint32_t id[U];
+    int cl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (d[u] < 0) continue;
+      const long k = kk[u];
+      x[u][0] = S.r[k];
+      x[u][1] = S.th[k];
+      x[u][2] = S.ph[k];
+      x[u][3] = S.ur[k];
+      x[u][4] = S.uth[k];
+      x[u][5] = S.uph[k];
+      x[u][6] = S.H0[k];
+      x[u][7] = S.herr[k];
+      x[u][8] = S.w[k];
+      x[u][9] = S.W[1][k];
+      x[u][10] = S.W[2][k];
+      x[u][11] = S.W[3][k];
+      qm[u] = S.qm[k];
+      fl[u] = S.flags[k];
+      it[u] = S.iters[k];
+      id[u] = S.id[k];
+      cl[u] = S.cell[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (d[u] < 0) continue;
+      const long t = d[u];
+      D.r[t] = x[u][0];
+      D.th[t] = x[u][1];
+      D.ph[t] = x[u][2];
+      D.ur[t] = x[u][3];
+      D.uth[t] = x[u][4];
+      D.uph[t] = x[u][5];
+      D.H0[t] = x[u][6];
+      D.herr[t] = x[u][7];
+      D.w[t] = x[u][8];
+      D.W[1][t] = x[u][9];
+      D.W[2][t] = x[u][10];
+      D.W[3][t] = x[u][11];
+      D.qm[t] = qm[u];
+      D.flags[t] = fl[u];
+      D.iters[t] = it[u];
+      D.id[t] = id[u];
+      D.cell[t] = cl[u];
+    }
   }
 }
 
@@ -320,7 +371,7 @@ void invalidate_deposit_plan(grpic_ctx* c) {
   if (c->dep_plan_meta) launch_fill(c, c->dep_plan_meta, 3 * sizeof(int));
 }
 
-void launch_sort(grpic_ctx* c) {
+void launch_sort(grpic_ctx* c, bool from_cells) {
   if (c->n == 0 || c->nr == 0) return;
   hipEvent_t ev;
   time_begin(c, GRPIC_K_SORT, &ev);
@@ -335,6 +386,7 @@ void launch_sort(grpic_ctx* c) {
   A.ntiles = c->ntiles;
   A.count = c->tile_count;
   A.offset = c->tile_offset;
+  A.cell = from_cells ? c->pv.cell : nullptr;
   dim3 g(grid_for(c->n, kSortChunk)), b(256);
   size_t sh = sizeof(int) * (c->ntiles + 1);
   hipLaunchKernelGGL(k_tile_count, g, b, sh, c->stream, A);
