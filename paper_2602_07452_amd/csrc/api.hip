@@ -9,6 +9,8 @@
 #include <memory>
 #include <mutex>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kerr_device.hpp"
 
 using namespace grpic;
@@ -373,17 +375,33 @@ void particles_loaded(grpic_ctx* c) {
 }
 
 // ---------------------------------------------------------------- step
+// Host ranges for tracing tools (roctx): one per part of the step, named
+// after the sub-steps of Sec. 2.1; they mark when the launches are issued
+// (and, for a captured graph, when it is recorded).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+};
+
 void step_kernels(grpic_ctx* c) {
   bool evolve = c->cfg.field_mode == GRPIC_FIELDS_EVOLVE;
   hipEvent_t ev;
   if (evolve) {
+    TraceRange t("grpic sub-steps 1-4: E, Faraday on both chains");
     time_begin(c, GRPIC_K_FIELDS, &ev);
     launch_fields_step_pre(c);
     time_end(c, GRPIC_K_FIELDS, ev);
   }
-  launch_push(c);
+  {
+    TraceRange t("grpic sub-step 5: gather and push (RK4, switch, implicit queue)");
+    launch_push(c);
+  }
   if (evolve) {
-    launch_deposit(c);
+    {
+      TraceRange t("grpic sub-step 6: deposit");
+      launch_deposit(c);
+    }
+    TraceRange t("grpic sub-steps 7-10: H, Ampere on both chains");
     time_begin(c, GRPIC_K_FIELDS, &ev);
     launch_fields_step_post(c);
     time_end(c, GRPIC_K_FIELDS, ev);
@@ -454,6 +472,7 @@ long inject_now(grpic_ctx* c) {
 }
 
 void run_step(grpic_ctx* c) {
+  TraceRange t(c->use_graph ? "grpic step (graph replay)" : "grpic step");
   if (!c->use_graph) {
     step_kernels(c);
     advance_host_state(c);
@@ -481,14 +500,21 @@ void run_step(grpic_ctx* c) {
     GRPIC_HIP(hipGraphLaunch(c->graph_exec[key], c->stream));
     advance_host_state(c);
   }
-  if (c->cfg.clean_every > 0 && c->steps % c->cfg.clean_every == 0)
+  if (c->cfg.clean_every > 0 && c->steps % c->cfg.clean_every == 0) {
+    TraceRange r("grpic divergence cleaning");
     launch_clean(c, c->cfg.clean_iters);  // eager, after the step
-  if (c->cfg.inj_every > 0 && c->steps % c->cfg.inj_every == 0) inject_now(c);
+  }
+  if (c->cfg.inj_every > 0 && c->steps % c->cfg.inj_every == 0) {
+    TraceRange r("grpic pair injection");
+    inject_now(c);
+  }
   if (c->cfg.sort_every > 0 && c->cfg.field_mode != GRPIC_FIELDS_NONE &&
-      c->steps % c->cfg.sort_every == 0)
+      c->steps % c->cfg.sort_every == 0) {
+    TraceRange r("grpic tile sort");
     // swaps the buffer sets (the other cached graphs apply); the full cycle
     // keeps every particle's node cell, which gives its tile directly
     launch_sort(c, c->cfg.field_mode == GRPIC_FIELDS_EVOLVE);
+  }
 }
 
 hipEvent_t take_event(grpic_ctx* c) {

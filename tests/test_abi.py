@@ -74,3 +74,17 @@ def test_kernel_group_names_match_the_header():
     text = open(G.HEADER).read()
     count = int(re.search(r"GRPIC_K_COUNT\s*=\s*(\d+)", text).group(1))
     assert count == len(G.KERNEL_NAMES)
+
+
+def test_step_is_marked_with_trace_ranges():
+    """The library marks the parts of a step (the sub-steps of Sec. 2.1, the
+    sort, cleaning and injection) with roctx ranges for tracing tools: it
+    imports the range calls, and the range names are in the library."""
+    out = subprocess.run(["nm", "-D", G.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    undefined = {l.split()[-1] for l in out.splitlines() if " U " in l}
+    assert {"roctxRangePushA", "roctxRangePop"} <= undefined
+    data = open(G.LIB_PATH, "rb").read()
+    for name in (b"grpic sub-steps 1-4", b"grpic sub-step 5", b"grpic sub-step 6",
+                 b"grpic sub-steps 7-10", b"grpic tile sort"):
+        assert name in data

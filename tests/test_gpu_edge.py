@@ -207,6 +207,19 @@ def test_zero_dt_is_half_the_courant_limit():
         G.Context(cfg)
 
 
+def test_time_step_above_the_courant_limit_is_refused():
+    """grpic_create refuses a full-cycle configuration whose dt exceeds the
+    grid's Courant limit (GRPIC_E_CFL) and accepts one just below it."""
+    cfg = _pic_cfg(n=64)
+    lim = G.cfl_dt(cfg)
+    cfg.dt = 1.01 * lim
+    with pytest.raises(G.GrpicError, match="error -2"):
+        G.Context(cfg)
+    cfg.dt = 0.99 * lim
+    with G.Context(cfg) as ctx:
+        assert ctx.get_config().dt == cfg.dt
+
+
 def test_nonfinite_particle_is_removed_and_isolated():
     """A particle whose step gives a non-finite state is flagged, counted and
     removed; it deposits nothing, the fields stay finite, and every other
