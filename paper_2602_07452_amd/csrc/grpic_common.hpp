@@ -51,8 +51,6 @@ struct StatRep {
 struct Stats {
   StatRep rep[kStatReps];
   unsigned int seg_count[kQueueSegs];  // entries in each queue segment
-  unsigned int work_counter;     // persistent-kernel work cursor
-  unsigned int guess_counter;    // learned-guess kernel work cursor
   unsigned int deposit_fallback; // deposit segments that used global atomics
   unsigned int cross_count;      // crossing moves queued by the deposit
 };

@@ -354,10 +354,12 @@ __global__ __launch_bounds__(64 * kGuessWaves) void k_mlp_guess(GuessArgs A) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   bf16* xs = Xs[w];
   float* ys = Ys[w];
-  for (;;) {
-    unsigned v0 = 0;
-    if (l == 0) v0 = atomicAdd(&A.st->guess_counter, 64u);
-    v0 = __shfl(v0, 0, 64);
+  // wave w of nw takes queue groups of 64 w, w + nw, ...: the work per group
+  // is the same, so fixed shares balance it without a shared work counter
+  // (whose serialised atomics made this kernel take twice as long)
+  const unsigned nw = gridDim.x * kGuessWaves;
+  for (unsigned grp = blockIdx.x * kGuessWaves + w;; grp += nw) {
+    const unsigned v0 = grp * 64u;
     if (v0 >= qn) break;
     const unsigned v = v0 + l;
     const bool act = v < qn;

@@ -9,9 +9,9 @@
 //    at every stage; the switch either accepts the step or appends the
 //    particle to the implicit queue (wave ballots, one atomic per block on
 //    one of kQueueSegs segment counters).
-//  * k_push_implicit: persistent kernel; each wave takes kGrab entries of
-//    the concatenated segments at a time from a device cursor until the
-//    queue is drained.
+//  * k_push_implicit: persistent kernel; its waves take groups of kGrab
+//    entries of the concatenated segments in fixed round-robin shares until
+//    the queue is drained.
 #include "deposit_device.hpp"
 #include "queue_device.hpp"
 
@@ -671,10 +671,12 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
   const unsigned qn = segment_prefix(A.st, pref);
   const ParticleView& P = A.p;
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    unsigned base = 0;
-    if (lane == 0) base = atomicAdd(&A.st->work_counter, kGrab);
-    base = __shfl(base, 0, 64);
+  // wave w of nw takes queue groups w, w + nw, w + 2 nw, ...: fixed shares,
+  // no shared work counter (every wave appending to one counter serialised
+  // the grabs: 0.47 against 0.42 ms per step on 2^27 particles)
+  const unsigned nw = gridDim.x * (blockDim.x >> 6);
+  for (unsigned grp = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);; grp += nw) {
+    const unsigned base = grp * kGrab;
     if (base >= qn) break;
     for (unsigned sub = 0; sub < kGrab; sub += 64) {
       unsigned v = base + sub + lane;
@@ -757,10 +759,6 @@ __global__ void k_reset_step(Stats* st) {
   for (int r = 0; r < kStatReps; ++r) {
     for (int i = t; i < kHistBins; i += blockDim.x) st->rep[r].herr_hist[i] = 0;
     if (t == 0) st->rep[r].alive = 0;
-  }
-  if (t == 0) {
-    st->work_counter = 0;
-    st->guess_counter = 0;
   }
 }
 

@@ -146,6 +146,50 @@ def test_collected_samples_match_oracle():
         assert np.all(np.abs(T[v] - t) <= 1e-6 * np.abs(t) + 1e-11 * np.maximum(np.abs(z), 1)), v
 
 
+@pytest.mark.parametrize("guess", [G.GUESS_RK4, G.GUESS_MLP])
+def test_collected_hybrid_samples_match_oracle(guess):
+    """Hyb2 passes its rejected particles to the implicit pass with the RK4
+    result as the base of the guess.  The samples collected from them carry
+    the network's features at z^n (z^n, q/m D, q/m B, alpha, beta^r) and,
+    as target, the converged step minus the RK4 result, both as the oracle
+    computes them; with the learned guess configured or not."""
+    n = 3000
+    a = 0.9
+    cfg = G.config_default(a=a, nr=64, nth=48, r_in=0.9 * rplus(a), r_out=50.0, dt=0.02,
+                           field_mode=G.FIELDS_STATIC, pusher=G.PUSH_HYB2,
+                           hyb_threshold=1e-15, max_particles=n, r_remove_in=rplus(a),
+                           r_remove_out=50.0, reflect=1, guess=guess)
+    g = oracle_grid(cfg)
+    P = push_params_from(cfg, O.FIELDS_GRID)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_ISO, n, SEED + 3, 2.0, 30.0, cfg.theta0,
+                           np.pi - cfg.theta0, 1.0)
+        G6 = gpu_fields_as_G(ctx)
+        before = ctx.get_particles()
+        ctx.mlp_collect(10 * n)
+        ctx.step(1)
+        after = ctx.get_particles()
+        X, T, valid = ctx.mlp_get_samples()
+    implicit = (after["flags"] & G.FLAG_IMPLICIT) != 0
+    assert 0 < len(X) == implicit.sum() < n and valid.all()
+    keys = _row_keys(before["z"].astype(np.float32))
+    rows = [keys[X[v, :6].tobytes()] for v in range(len(X))]
+    assert len(set(rows)) == len(rows) and implicit[rows].all()
+    colmax = np.abs(X).max(axis=0)
+    for v in range(0, len(X), max(1, len(X) // 200)):
+        k = rows[v]
+        z, qm = before["z"][k], before["qm"][k]
+        D, B = O.gather(g, G6, z[0], z[1])
+        m = O.metric(cfg.a, z[0], z[1])
+        feat = np.concatenate([z, qm * D, qm * B, [m[0], m[1]]])
+        assert np.all(np.abs(X[v] - feat) <= 1.2e-7 * np.abs(feat) + 1e-12 * colmax), v
+        zr, _ = O.step_rk4(P, qm, z, grid=g, G=G6)
+        zi, it, _ = O.step_imr(P, qm, z, guess=zr, grid=g, G=G6)
+        t = zi - zr
+        assert np.all(np.abs(T[v] - t) <= 1e-6 * np.abs(t) + 1e-11 * np.maximum(np.abs(z), 1)), v
+
+
 # ------------------------------------------------------------ effect
 def _mean_iters(d0, d1):
     h = d1["iter_hist"] - d0["iter_hist"]
