@@ -805,6 +805,7 @@ def main():
         "mean_implicit_iterations": float(iters / max(impl, 1)),
         "h_error": herr_percentiles(d1["herr_hist"]),
         "deposit_fallback_blocks": int(d1["deposit_fallback"] - d0["deposit_fallback"]),
+        "deposit_outside_box": int(d1["deposit_outside"] - d0["deposit_outside"]),
         "roofline": roof,
         "measured_peaks": peaks,
         "autotune": tune,

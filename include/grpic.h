@@ -335,6 +335,9 @@ typedef struct grpic_diag {
                             on-chip bins (cumulative)                      */
   long nonfinite;        /* particles removed for a non-finite state
                             (cumulative, also counted in removed)          */
+  long deposit_outside;  /* particles deposited through global atomics
+                            because they had left the node box planned for
+                            their chunk at the last sort (cumulative)      */
 } grpic_diag;
 /* The counters above (synchronises the stream).  The energy violation is
  * the hybrid switch quantity of Sec. 3.1.2 (|H - H_0| / |H_0| for neutral

@@ -66,7 +66,7 @@ class Diag(C.Structure):
                 ("implicit_steps", C.c_long), ("noconv", C.c_long),
                 ("reflected", C.c_long), ("iter_hist", C.c_long * HIST_BINS),
                 ("herr_hist", C.c_long * HIST_BINS), ("deposit_fallback", C.c_long),
-                ("nonfinite", C.c_long)]
+                ("nonfinite", C.c_long), ("deposit_outside", C.c_long)]
 
 
 def lib():
@@ -292,7 +292,8 @@ class Context:
                 "implicit_steps": d.implicit_steps, "noconv": d.noconv,
                 "reflected": d.reflected, "iter_hist": np.array(d.iter_hist[:]),
                 "herr_hist": np.array(d.herr_hist[:]),
-                "deposit_fallback": d.deposit_fallback, "nonfinite": d.nonfinite}
+                "deposit_fallback": d.deposit_fallback, "nonfinite": d.nonfinite,
+                "deposit_outside": d.deposit_outside}
 
     def inject(self):
         """Pair injection now (Sec. 3.3); returns the particles added."""

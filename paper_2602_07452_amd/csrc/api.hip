@@ -353,6 +353,7 @@ void free_all(grpic_ctx* c) {
   dfree(c->dep_plan);
   dfree(c->dep_plan_off);
   dfree(c->dep_plan_meta);
+  dfree(c->dep_plan_box);
   dfree(c->stats);
   mlp_free(c);
 }
@@ -1076,6 +1077,7 @@ int grpic_get_diagnostics(grpic_ctx* c, grpic_diag* out) {
       }
     }
     out->deposit_fallback = (long)s.deposit_fallback;
+    out->deposit_outside = (long)s.deposit_outside;
   });
 }
 

@@ -24,10 +24,12 @@ struct DepArgs {
   int nr, nth;
   double inv_nr;       // 1 / nr, to split a cell index without an integer division
   unsigned* fallback;  // blocks that used global atomics (diagnostic)
+  unsigned long long* outside;  // particles outside their planned box (diagnostic)
   int* xqueue;         // particles whose move crosses a node-cell boundary
   unsigned* xcount;
   const int* plan;       // chunk starts of the last sort (see chunk_range)
   const int* plan_meta;  // {chunks, particles at the sort, valid}; null: no plan
+  const int4* plan_box;  // node box {p0, q0, bw, bh} of each planned chunk
 };
 
 // Particle range [beg, end) of deposit chunk b (false: past the last
@@ -35,14 +37,19 @@ struct DepArgs {
 // runs of tiles whose node box fits the LDS bins (the dead particles the
 // sort put last need no deposit) and the rest are the particles appended
 // since, kDepChunk at a time; without one, equal chunks of the whole array.
-// Blocks stride over the chunks, so any grid size covers them all.
-__device__ __forceinline__ bool chunk_range(const DepArgs& A, long b, long& beg, long& end) {
+// Blocks stride over the chunks, so any grid size covers them all.  box:
+// the planned node box of the chunk (bw = 0: none, the chunk's own box is
+// measured).
+__device__ __forceinline__ bool chunk_range(const DepArgs& A, long b, long& beg, long& end,
+                                            int4& box) {
   long first = 0;
+  box = make_int4(0, 0, 0, 0);
   if (A.plan_meta && A.plan_meta[2]) {
     const long total = A.plan_meta[0];
     if (b < total) {
       beg = A.plan[b];
       end = min((long)A.plan[b + 1], A.p.n);
+      box = A.plan_box[b];
       return true;
     }
     b -= total;
@@ -79,7 +86,7 @@ struct GlobalSink {
 
 struct LdsSink {
   long long* bins;  // 4 arrays of bw * bh
-  int p0, q0, bw, n;
+  int p0, q0, bw, bh, n;  // n = bw * bh
   __device__ __forceinline__ long long* slot(int a, int i, int j) const {
     return bins + a * n + (j - q0) * bw + (i - p0);
   }
@@ -285,7 +292,6 @@ __device__ void deposit_crossing(const DepArgs& A, const Sink& S, const XRec& x)
 
 constexpr int kDepBlock = 512;
 constexpr int kDepSub = 2048;     // segment length when the chunk box is too big
-constexpr int kDepBins = 2048;    // LDS nodes per array (4 arrays x 16 KB)
 
 // Bounding box (node-cell columns box[0..1], rows box[2..3]) of the old and
 // new cells of the charged particles in [beg, end); block-uniform result.
@@ -358,7 +364,18 @@ __device__ __forceinline__ void flush_list(const DepArgs& A, WaveList& X) {
   X.n = 0;
 }
 
-template <class Sink>
+// the planned box holds both node cells of the move (the four nodes of each)
+__device__ __forceinline__ bool in_box(const DepArgs& A, const LdsSink& L, int c0, int c1) {
+  int p0, q0, p1, q1;
+  split_cell(A, c0, p0, q0);
+  split_cell(A, c1, p1, q1);
+  const int pl = L.p0, ph = L.p0 + L.bw - 2, ql = L.q0, qh = L.q0 + L.bh - 2;
+  return min(p0, p1) >= pl && max(p0, p1) <= ph && min(q0, q1) >= ql && max(q0, q1) <= qh;
+}
+
+// CHECKED (an LDS sink over a planned box): a particle whose cells left
+// the box since the sort goes to the global accumulators instead
+template <bool CHECKED = false, class Sink>
 __device__ __forceinline__ void deposit_one(const DepArgs& A, const Sink& S, WaveList& X,
                                             const PRec& r, long k, long end) {
   const int lane = threadIdx.x & 63;
@@ -366,7 +383,18 @@ __device__ __forceinline__ void deposit_one(const DepArgs& A, const Sink& S, Wav
   if (k < end) {
     PDep d;
     unpack_rec(r, d);
-    if (d.act) cross = !deposit_particle(A, S, d);
+    if (d.act) {
+      if constexpr (CHECKED) {
+        const bool inside = in_box(A, S, d.c0, d.c1);
+        if (inside) cross = !deposit_particle(A, S, d);
+        else cross = !deposit_particle(A, GlobalSink{&A.acc, A.nr}, d);
+        const unsigned long long o = __ballot(!inside);
+        if (o && lane == (int)__ffsll((long long)o) - 1)
+          atomicAdd(A.outside, (unsigned long long)__popcll(o));
+      } else {
+        cross = !deposit_particle(A, S, d);
+      }
+    }
   }
   unsigned long long m = __ballot(cross);
   if (m) {
@@ -379,7 +407,7 @@ __device__ __forceinline__ void deposit_one(const DepArgs& A, const Sink& S, Wav
 // Three records rotate (no register copies, which would wait for their
 // loads): while one is accumulated the next two are in flight.  Loads use
 // clamped indices; slots past the end are skipped.
-template <class Sink>
+template <bool CHECKED = false, class Sink>
 __device__ __forceinline__ void deposit_range(const DepArgs& A, long beg, long end,
                                               const Sink& S, WaveList& X) {
   const ParticleView& P = A.p;
@@ -389,11 +417,11 @@ __device__ __forceinline__ void deposit_range(const DepArgs& A, long beg, long e
   load_rec(P, min(beg + B + t, last), b);
   for (long kb = beg; kb < end; kb += 3 * B) {  // uniform trip count
     load_rec(P, min(kb + 2 * B + t, last), c);
-    deposit_one(A, S, X, a, kb + t, end);
+    deposit_one<CHECKED>(A, S, X, a, kb + t, end);
     load_rec(P, min(kb + 3 * B + t, last), a);
-    deposit_one(A, S, X, b, kb + B + t, end);
+    deposit_one<CHECKED>(A, S, X, b, kb + B + t, end);
     load_rec(P, min(kb + 4 * B + t, last), b);
-    deposit_one(A, S, X, c, kb + 2 * B + t, end);
+    deposit_one<CHECKED>(A, S, X, c, kb + 2 * B + t, end);
   }
 }
 
@@ -413,11 +441,29 @@ __global__ __launch_bounds__(256) void k_deposit_crossing(DepArgs A) {
 
 __global__ void k_reset_xcount(unsigned* x) { *x = 0u; }
 
-// Per chunk of (tile-sorted) particles (chunk_range): the node box covering
-// every old and new cell of the chunk is accumulated in LDS and flushed
-// once.  A chunk whose box does not fit is redone in segments of
-// kDepSub particles with their own boxes; a segment that still does not fit
-// uses global atomics.
+// the block's LDS bins into the global accumulators (nonzero bins only)
+__device__ __forceinline__ void flush_bins(const DepArgs& A, const LdsSink& L) {
+  GlobalSink Gs{&A.acc, A.nr};
+  for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
+    long long v = L.bins[i];
+    if (v == 0) continue;
+    int a = i / L.n, r = i - a * L.n;
+    int jj = r / L.bw, ii = r - jj * L.bw;
+    // r-flux lives on cells (i < nr), theta-flux on rows j < nth
+    if ((a == 2 && L.p0 + ii >= A.nr) || (a == 3 && L.q0 + jj >= A.nth)) continue;
+    atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, L.p0 + ii, L.q0 + jj)),
+              static_cast<unsigned long long>(v));
+  }
+}
+
+// Per chunk of (tile-sorted) particles (chunk_range), summed in LDS bins
+// over a node box and flushed once.  A chunk of the sort's plan comes with
+// its group's box: one pass, and the few particles that have drifted out
+// of it since the sort go to the global accumulators.  Other chunks
+// (particles appended since the sort, no plan) first measure the box of
+// their old and new cells; a chunk whose box does not fit is redone in
+// segments of kDepSub particles with their own boxes, and a segment that
+// still does not fit uses global atomics.
 __global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
   __shared__ long long bins[4 * kDepBins];
   __shared__ int box[4];
@@ -425,7 +471,19 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
   WaveList X{xlist + (threadIdx.x >> 6) * kXList, 0};
   for (long b = blockIdx.x;; b += gridDim.x) {  // uniform over the block
     long beg, end;
-    if (!chunk_range(A, b, beg, end)) break;
+    int4 pb;
+    if (!chunk_range(A, b, beg, end, pb)) break;
+    if (pb.z > 0) {
+      if (beg >= end) continue;
+      LdsSink L{bins, pb.x, pb.y, pb.z, pb.w, pb.z * pb.w};
+      __syncthreads();  // the previous chunk's flush is done with the bins
+      for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
+      __syncthreads();
+      deposit_range<true>(A, beg, end, L, X);
+      __syncthreads();
+      flush_bins(A, L);
+      continue;
+    }
     for (int pass = 0; pass < 2; ++pass) {
       const long seg = pass == 0 ? kDepChunk : kDepSub;
       bool redo = false;
@@ -445,22 +503,12 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepArgs A) {
           deposit_range(A, sb, se, GlobalSink{&A.acc, A.nr}, X);
           continue;
         }
-        LdsSink L{bins, bp0, bq0, bw, bw * bh};
+        LdsSink L{bins, bp0, bq0, bw, bh, bw * bh};
         for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
         __syncthreads();
         deposit_range(A, sb, se, L, X);
         __syncthreads();
-        GlobalSink Gs{&A.acc, A.nr};
-        for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) {
-          long long v = bins[i];
-          if (v == 0) continue;
-          int a = i / L.n, r = i - a * L.n;
-          int jj = r / bw, ii = r - jj * bw;
-          // r-flux lives on cells (i < nr), theta-flux on rows j < nth
-          if ((a == 2 && bp0 + ii >= A.nr) || (a == 3 && bq0 + jj >= A.nth)) continue;
-          atomicAdd(reinterpret_cast<unsigned long long*>(Gs.slot(a, bp0 + ii, bq0 + jj)),
-                    static_cast<unsigned long long>(v));
-        }
+        flush_bins(A, L);
       }
       if (!redo) break;
     }
@@ -577,7 +625,8 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const do
   const ParticleView& P = A.p;
   for (long b = blockIdx.x;; b += gridDim.x) {  // uniform over the block
     long beg, end;
-    if (!chunk_range(A, b, beg, end)) break;
+    int4 unused_box;  // equal chunks (no plan): always zero
+    if (!chunk_range(A, b, beg, end, unused_box)) break;
     __syncthreads();  // the previous chunk is done with box and bins
     if (threadIdx.x == 0) {
       box[0] = 1 << 30;
@@ -614,7 +663,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const do
           paper_particle(A, Gs, k, W1, W2, W3, cell, dt);
       continue;
     }
-    LdsSink L{bins, bp0, bq0, bw, bw * bh};
+    LdsSink L{bins, bp0, bq0, bw, bh, bw * bh};
     for (int i = threadIdx.x; i < 4 * L.n; i += kDepBlock) bins[i] = 0;
     __syncthreads();
     for (long k = beg + threadIdx.x; k < end; k += kDepBlock)
@@ -643,10 +692,12 @@ static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int
   A.nth = c->nth;
   A.inv_nr = 1.0 / c->nr;
   A.fallback = &c->stats->deposit_fallback;
+  A.outside = nullptr;  // no planned boxes here
   // equal chunks: its per-particle work is large, so the few chunks whose
   // box misses the LDS bins cost less than the plan's many small chunks
   A.plan = nullptr;
   A.plan_meta = nullptr;
+  A.plan_box = nullptr;
   hipLaunchKernelGGL(k_deposit_paper, dim3(deposit_blocks(c)), dim3(kDepBlock), 0,
                      c->stream, A, W[1], W[2], W[3], cell, c->cfg.dt);
   GRPIC_HIP(hipGetLastError());
@@ -730,10 +781,12 @@ void launch_deposit(grpic_ctx* c) {
     A.nth = c->nth;
     A.inv_nr = 1.0 / c->nr;
     A.fallback = &c->stats->deposit_fallback;
+    A.outside = &c->stats->deposit_outside;
     A.xqueue = c->xqueue;
     A.xcount = &c->stats->cross_count;
     A.plan = c->dep_plan;
     A.plan_meta = c->dep_plan_meta;
+    A.plan_box = c->dep_plan_box;
     hipLaunchKernelGGL(k_reset_xcount, dim3(1), dim3(1), 0, c->stream, A.xcount);
     hipLaunchKernelGGL(k_deposit, dim3(deposit_blocks(c)), dim3(kDepBlock), 0,
                        c->stream, A);
@@ -761,6 +814,7 @@ void launch_deposit_initial(grpic_ctx* c) {
     A.inv_nr = 1.0 / c->nr;
     A.plan = nullptr;
     A.plan_meta = nullptr;
+    A.plan_box = nullptr;
     if (c->cfg.deposit_mode == GRPIC_DEPOSIT_PAPER)
       launch_deposit_paper(c, P.W, P.cell);  // rho and J at the loaded state
     else

@@ -53,6 +53,7 @@ struct Stats {
   unsigned int seg_count[kQueueSegs];  // entries in each queue segment
   unsigned int deposit_fallback; // deposit segments that used global atomics
   unsigned int cross_count;      // crossing moves queued by the deposit
+  unsigned long long deposit_outside;  // particles outside their planned box
 };
 
 // fixed-point charge accumulators (int64, deterministic under atomics)
@@ -127,6 +128,7 @@ struct grpic_ctx {
   int* dep_plan = nullptr;
   int* dep_plan_off = nullptr;
   int* dep_plan_meta = nullptr;
+  int4* dep_plan_box = nullptr;  // node box of each planned chunk (see plan)
   long dep_plan_cap = 0;  // entries of dep_plan
   int plan_groups = 0;    // tile groups of the current plan layout
   double qw_max = 0;
@@ -198,6 +200,7 @@ void launch_clean(grpic_ctx* c, int iters);  // Sec. 2.4, both D chains
 constexpr int kInjMjK = 4096;                 // intervals of the MJ table
 long launch_inject(grpic_ctx* c, const double* mj, int mj_k, double mj_h);
 constexpr int kDepChunk = 8192;  // particles per deposit block at most
+constexpr int kDepBins = 2048;   // LDS nodes per deposit array
 // deposit blocks to launch for the current particle count and plan layout
 long deposit_blocks(const grpic_ctx* c);
 void invalidate_deposit_plan(grpic_ctx* c);

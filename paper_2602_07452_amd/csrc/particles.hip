@@ -314,11 +314,43 @@ __global__ __launch_bounds__(256) void k_plan_count(const int* tile_end, int nti
   nch[g] = (e - s + kDepChunk - 1) / kDepChunk;
 }
 
+// The node box of a group: its tiles' cells (serpentine order keeps them
+// together), widened on every side by the largest margin of at most
+// kPlanMargin cells for which the box still fits the deposit's LDS bins,
+// so that particles which drift until the next sort mostly stay inside.
+// {p0, q0, bw, bh} in nodes; bw = 0 when even the bare tiles do not fit.
+constexpr int kPlanMargin = 8;
+
+struct PlanGeom {
+  int tile_r, tile_th, ntr, nr, nth;
+};
+
+__device__ int4 group_box(const PlanGeom& G, int t0, int t1) {
+  int p0 = 1 << 30, p1 = -1, q0 = 1 << 30, q1 = -1;
+  for (int t = t0; t < t1; ++t) {
+    const int tq = t / G.ntr, tc = t - tq * G.ntr;
+    const int tp = (tq & 1) ? G.ntr - 1 - tc : tc;
+    p0 = min(p0, tp * G.tile_r);
+    p1 = max(p1, min((tp + 1) * G.tile_r, G.nr) - 1);
+    q0 = min(q0, tq * G.tile_th);
+    q1 = max(q1, min((tq + 1) * G.tile_th, G.nth) - 1);
+  }
+  for (int m = kPlanMargin; m >= 0; --m) {
+    const int a0 = max(p0 - m, 0), a1 = min(p1 + m, G.nr - 1);
+    const int b0 = max(q0 - m, 0), b1 = min(q1 + m, G.nth - 1);
+    const int bw = a1 - a0 + 2, bh = b1 - b0 + 2;  // nodes of cells a0..a1, b0..b1
+    if (bw * bh <= kDepBins) return make_int4(a0, b0, bw, bh);
+  }
+  return make_int4(0, 0, 0, 0);
+}
+
 // chunk starts from the groups' chunk offsets; start[total] = end of the
-// particles alive at the sort; meta = {total, n, 1}
+// particles alive at the sort; meta = {total, n, 1}; box: each chunk's
+// group box
 __global__ __launch_bounds__(256) void k_plan_write(const int* tile_end, int ntiles, int K,
                                                     int ngroups, const int* off, int n,
-                                                    int* start, int* meta) {
+                                                    int* start, int* meta, PlanGeom G,
+                                                    int4* box) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g > ngroups) return;
   if (g == ngroups) {
@@ -331,7 +363,11 @@ __global__ __launch_bounds__(256) void k_plan_write(const int* tile_end, int nti
   }
   const int t0 = g * K;
   const int s = t0 == 0 ? 0 : tile_end[t0 - 1];
-  for (int i = off[g]; i < off[g + 1]; ++i) start[i] = s + (i - off[g]) * kDepChunk;
+  const int4 b = group_box(G, t0, min(t0 + K, ntiles));
+  for (int i = off[g]; i < off[g + 1]; ++i) {
+    start[i] = s + (i - off[g]) * kDepChunk;
+    box[i] = b;
+  }
 }
 
 void plan_deposit_chunks(grpic_ctx* c) {
@@ -341,10 +377,12 @@ void plan_deposit_chunks(grpic_ctx* c) {
   if (need > c->dep_plan_cap || !c->dep_plan_meta) {
     dfree(c->dep_plan);
     dfree(c->dep_plan_off);
+    dfree(c->dep_plan_box);
     if (!c->dep_plan_meta) c->dep_plan_meta = dalloc<int>(3);
     c->dep_plan_cap = 0;
     c->dep_plan = dalloc<int>(need);
     c->dep_plan_off = dalloc<int>(need);
+    c->dep_plan_box = dalloc<int4>(need);
     c->dep_plan_cap = need;
   }
   c->plan_groups = ngroups;
@@ -355,9 +393,11 @@ void plan_deposit_chunks(grpic_ctx* c) {
                      c->ntiles, K, ngroups, c->tile_count);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, c->stream, c->tile_count,
                      c->dep_plan_off, ngroups + 1);
+  PlanGeom G{c->cfg.tile_r, c->cfg.tile_th, (c->nr + c->cfg.tile_r - 1) / c->cfg.tile_r,
+             c->nr, c->nth};
   hipLaunchKernelGGL(k_plan_write, dim3(gb), dim3(256), 0, c->stream, c->tile_offset,
                      c->ntiles, K, ngroups, c->dep_plan_off, (int)c->n, c->dep_plan,
-                     c->dep_plan_meta);
+                     c->dep_plan_meta, G, c->dep_plan_box);
   GRPIC_HIP(hipGetLastError());
 }
 

@@ -2,9 +2,9 @@
 reach, against the oracle: the implicit iteration stopped at its cap
 (non-convergence, Sec. 2.2.2), the restart from z^n when the iteration from
 the learned guess does not converge, and the deposit's overflow paths
-(Sec. 2.3): the second pass over short segments and the global-atomic
-fallback of the conserving deposit, and the global fallback of the paper's
-current."""
+(Sec. 2.3): the second pass over short segments, the global-atomic
+fallback and the particles outside their planned box in the conserving
+deposit, and the global fallback of the paper's current."""
 import numpy as np
 import pytest
 
@@ -189,6 +189,31 @@ def test_deposit_second_pass_of_injected_particles_matches_oracle():
     rows = np.searchsorted(g.tn, P0["th"][first])
     cols = np.searchsorted(g.rn, P0["r"][first])
     assert (np.ptp(rows) + 2) * (np.ptp(cols) + 2) > 2048
+    assert d1["deposit_fallback"] == d0["deposit_fallback"]
+    _deposit_matches(cfg, P0, P1, S1)
+
+
+def test_deposit_outside_the_planned_box_matches_oracle():
+    """The sort plans a node box for each deposit chunk (its tiles widened
+    by a margin); a particle that has left that box since the sort is
+    deposited through global atomics.  No re-sort for 200 steps of hot
+    plasma on a 128 x 128 grid of 16 x 16 tiles lets particles near the
+    horizon, where the cells are small, drift out of their boxes: the GPU
+    counts them, and the deposit of the next step is the oracle's."""
+    cfg = _pic_cfg(20000, 128, 128, 16, 16, sort_every=0)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 123, rplus(cfg.a),
+                           18.0, cfg.theta0, np.pi - cfg.theta0, 1.0, w=2e-3)
+        ctx.step(200)
+        P0 = ctx.get_particles()
+        d0 = ctx.diagnostics()
+        ctx.step(1)
+        d1 = ctx.diagnostics()
+        P1, S1 = ctx.get_particles(), levels(ctx)
+    outside = d1["deposit_outside"] - d0["deposit_outside"]
+    print(f"particles outside their planned box in the last step: {outside}")
+    assert outside > 0
     assert d1["deposit_fallback"] == d0["deposit_fallback"]
     _deposit_matches(cfg, P0, P1, S1)
 
