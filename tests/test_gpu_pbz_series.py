@@ -69,9 +69,11 @@ def test_split_monopole_pbz_series_matches_oracle():
     p = oracle_particles(P0)
     P = push_params_from(cfg, O.FIELDS_GRID)
     series_orc = []
-    for _ in range(STEPS):
+    for s in range(STEPS):
         O.pic_step(P, g, F, p, absorber=[cfg.r_abs, cfg.chi0, cfg.lambda_abs])
         series_orc.append(O.poynting(g, F.Dn, F.Bn))
+        if (s + 1) % 20 == 0:
+            print(f"oracle step {s + 1} of {STEPS}", flush=True)
     sg, so = np.array(series_gpu), np.array(series_orc)
     # interior radii (the ends use one-sided averages)
     sg, so = sg[:, 1:-1], so[:, 1:-1]
