@@ -290,6 +290,10 @@ struct GatherLoads {
   float2 c[12];
   double rn0, rn1, irn, rh0, rh1, irh;
   int pn, ph, qn, qh;
+  // with gather_coefs: each component's corners in FP64 as the value at the
+  // lower radial corner and the radial difference, for the lower (v0, d0)
+  // and upper (v1, d1) corner row; the order of gather_interp's D, B
+  double v0[6], d0[6], v1[6], d1[6];
 };
 
 __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView& F,
@@ -354,6 +358,41 @@ __device__ __forceinline__ void gather_interp(const GridView& g, double r, doubl
   B[0] = lerp2(c[6], c[7], frn, fth) * isg;
   B[1] = lerp2(c[8], c[9], frh, ftn) * isg;
   B[2] = lerp2(c[10], c[11], frh, fth) * isg;
+}
+
+// the FP64 coefficients of the settled corners (once per loaded cell set;
+// interpolating from them gives exactly what gather_interp gives)
+__device__ __forceinline__ void gather_coefs(GatherLoads& L) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const double v00 = L.c[2 * j].x, v10 = L.c[2 * j].y;
+    const double v01 = L.c[2 * j + 1].x, v11 = L.c[2 * j + 1].y;
+    L.v0[j] = v00;
+    L.d0[j] = v10 - v00;
+    L.v1[j] = v01;
+    L.d1[j] = v11 - v01;
+  }
+}
+
+__device__ __forceinline__ double lerp2c(const GatherLoads& L, int j, double fr, double ft) {
+  const double b0 = L.v0[j] + fr * L.d0[j];
+  const double b1 = L.v1[j] + fr * L.d1[j];
+  return b0 + ft * (b1 - b0);
+}
+
+// gather_interp from the coefficients of gather_coefs
+__device__ __forceinline__ void gather_interp_coefs(const GridView& g, double r, double th,
+                                                    double isg, const GatherLoads& L,
+                                                    double* D, double* B) {
+  const double frn = clamp01((r - L.rn0) * L.irn), frh = clamp01((r - L.rh0) * L.irh);
+  const double ftn = clamp01((th - theta_node(g, L.qn)) * g.inv_dth);
+  const double fth = clamp01((th - theta_half(g, L.qh)) * g.inv_dth);
+  D[0] = lerp2c(L, 0, frh, ftn) * isg;
+  D[1] = lerp2c(L, 1, frn, fth) * isg;
+  D[2] = lerp2c(L, 2, frn, ftn) * isg;
+  B[0] = lerp2c(L, 3, frn, fth) * isg;
+  B[1] = lerp2c(L, 4, frh, ftn) * isg;
+  B[2] = lerp2c(L, 5, frh, fth) * isg;
 }
 
 __device__ __forceinline__ void gather_finish(const GridView& g, const FieldView& F,

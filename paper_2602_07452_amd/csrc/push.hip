@@ -89,7 +89,10 @@ __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
 // reused without memory traffic while the point stays in those cells (the
 // implicit iterates, whose points move by far less than a cell); a miss
 // loads the new cells into gc, issued before the gravity terms.
-template <bool GRID, bool SPLIT = false, bool CACHE = false>
+// COEFS (with CACHE): the cache holds the corners as FP64 interpolation
+// coefficients, converted once per loaded cell set instead of at every use
+// (more registers; the explicit push has them to spare at two waves per SIMD)
+template <bool GRID, bool SPLIT = false, bool CACHE = false, bool COEFS = false>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      const double* z, double s, double c, double* f,
                                      double* pw, double* e = nullptr,
@@ -141,8 +144,16 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
   if constexpr (CACHE) {
     if (charged) {
-      if (!hit) gather_settle(A.g, A.f, r, *gc);
-      gather_interp(A.g, r, z[1], isg, *gc, D, B);
+      if constexpr (COEFS) {
+        if (!hit) {
+          gather_settle(A.g, A.f, r, *gc);
+          gather_coefs(*gc);
+        }
+        gather_interp_coefs(A.g, r, z[1], isg, *gc, D, B);
+      } else {
+        if (!hit) gather_settle(A.g, A.f, r, *gc);
+        gather_interp(A.g, r, z[1], isg, *gc, D, B);
+      }
     }
   } else if constexpr (SPLIT) {
     if (charged) gather_finish(A.g, A.f, r, z[1], isg, gl, D, B);
@@ -192,7 +203,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   double k[6], acc[6], y[6], p, pacc, s, c;
   gc.pn = -1;
   fsincos(z[1], s0, c0);
-  eval<GRID, false, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc);
+  eval<GRID, false, CACHE, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] = k[i];
@@ -200,7 +211,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc = p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
+  eval<GRID, false, CACHE, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
@@ -208,7 +219,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc += 2.0 * p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
+  eval<GRID, false, CACHE, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] += 2.0 * k[i];
@@ -216,7 +227,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   }
   pacc += 2.0 * p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
-  eval<GRID, false, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
+  eval<GRID, false, CACHE, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
   const double c6 = dt / 6.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) out[i] = z[i] + c6 * (acc[i] + k[i]);
