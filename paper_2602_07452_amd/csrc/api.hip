@@ -151,9 +151,9 @@ void alloc_particles(grpic_ctx* c, long cap) {
   P.t = c->cfg.field_mode == GRPIC_FIELDS_NONE ? dalloc<double>(n) : nullptr;
   if (c->cfg.pusher != GRPIC_PUSH_RK4) {
     // explicit-pass block b appends to segment b % kQueueSegs, so a segment
-    // holds at most ceil(blocks / kQueueSegs) blocks of 256 entries
-    long blocks = (n + 255) / 256;
-    c->seg_cap = (unsigned)(((blocks + kQueueSegs - 1) / kQueueSegs) * 256);
+    // holds at most ceil(blocks / kQueueSegs) blocks of kPushBlock entries
+    long blocks = (n + kPushBlock - 1) / kPushBlock;
+    c->seg_cap = (unsigned)(((blocks + kQueueSegs - 1) / kQueueSegs) * kPushBlock);
     size_t qlen = (size_t)c->seg_cap * kQueueSegs;
     c->queue = dalloc<int>(qlen);
     // first iterates (RK4 result, learned or collected Euler guess)

@@ -39,6 +39,7 @@ struct ParticleView {
 // the host sums the replicas.
 constexpr int kStatReps = 64;
 constexpr int kQueueSegs = 256;  // the implicit queue is split in segments
+constexpr int kPushBlock = 64;   // threads per block of the explicit push
 
 struct StatRep {
   unsigned long long implicit_steps, noconv, removed, reflected, alive;
