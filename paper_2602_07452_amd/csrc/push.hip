@@ -476,8 +476,10 @@ __device__ int ham_dg(const PushArgs& A, double dt, const double* z, double* zk)
 // quadrature of (q/m) E_i dx^i/dt)
 // zn: the new state; s0, c0: sin, cos of the old angle z0
 // (*sn, *cn: sin, cos of zn[1], for finalize)
+// H0 (the particle's initial H) is read only for a neutral particle: the
+// charged ones never wait for that load
 __device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
-                                               double H0, double e0,
+                                               const double* H0, double e0,
                                                const double* zn, double Wq,
                                                double z0, double s0, double c0,
                                                double* sn, double* cn) {
@@ -486,7 +488,10 @@ __device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
   *sn = s;
   *cn = c;
   double e1 = energy_sc(A.a, zn, s, c);
-  if (qm == 0.0) return fabs(e1 - H0) / fabs(H0);
+  if (qm == 0.0) {
+    const double h0 = *H0;
+    return fabs(e1 - h0) / fabs(h0);
+  }
   return fabs(e1 - e0 - Wq) / fabs(e0);
 }
 
@@ -622,7 +627,7 @@ void k_push_explicit(PushArgs A) {
       double Wq, e0, s0, c0, sn, cn;
       GatherLoads gc;
       rk4<GRID, CACHE && GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0, gc);
-      double v = switch_value(A, qm, P.H0[k], e0, trial, Wq, z[1], s0, c0, &sn, &cn);
+      double v = switch_value(A, qm, P.H0 + k, e0, trial, Wq, z[1], s0, c0, &sn, &cn);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
         accept = v < A.thr;
@@ -754,7 +759,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
       }
       double e0 = qm != 0.0 ? energy_sc(A.a, z, s0, c0) : 0.0;
       double sn, cn;
-      double v2 = switch_value(A, qm, P.H0[k], e0, zk, Wq, z[1], s0, c0, &sn, &cn);
+      double v2 = switch_value(A, qm, P.H0 + k, e0, zk, Wq, z[1], s0, c0, &sn, &cn);
       finalize<EVOLVE>(A, k, z, zk, v2, it, fl, ls, s0, c0, sn, cn, col);
       if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
     }
