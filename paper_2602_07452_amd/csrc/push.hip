@@ -189,11 +189,12 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
 // RK4; *e0 = energy e at z (from the first stage)
 // classical RK4 with the fields re-gathered at every stage; s0, c0 (out):
 // sin, cos of z[1], from which the stage angles are reached by short series
-// CACHE: the stages reuse the field corners of the previous stage's cells
-// while they stay in them (a step moves a particle by a fraction of a cell,
-// so three of the four stage gathers mostly need no memory round trip; the
-// cached corners raise the explicit push from 154 to 184 VGPRs, three to
-// two waves per SIMD, and still take 3.5 % off its time on 2^27 particles)
+// CACHE: the stages reuse the field corners of the previous stage's cells,
+// held as FP64 interpolation coefficients, while they stay in them (a step
+// moves a particle by a fraction of a cell, so three of the four stage
+// gathers mostly need no memory round trip; the cache raises the explicit
+// push from 154 to 232 VGPRs, three to two waves per SIMD, and still takes
+// 5 % off its time on 2^27 particles)
 // gc (out): the gather cells of the last stage (pn = -1 without the cache)
 template <bool GRID, bool CACHE = false>
 __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
