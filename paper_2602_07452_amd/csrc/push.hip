@@ -96,7 +96,7 @@ template <bool GRID, bool SPLIT = false, bool CACHE = false, bool COEFS = false>
 __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      const double* z, double s, double c, double* f,
                                      double* pw, double* e = nullptr,
-                                     GatherLoads* gc = nullptr) {
+                                     GatherLoads* gc = nullptr, bool issued = false) {
   const double a = A.a, a2 = a * a, r = z[0], ur = z[3], ut = z[4], up = z[5];
   const double s2 = s * s, sc = s * c;
   // one inverse square root y = (rho2 S)^(-1/2) gives alpha = sqrt(rho2 / S)
@@ -113,8 +113,11 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   bool hit = false;
   if (charged) {
     if constexpr (CACHE) {
-      hit = gather_hit(A.g, r, z[1], *gc);
-      if (!hit) gather_issue(A.g, A.f, r, z[1], *gc);
+      // issued: the caller has issued this point's loads into gc already
+      if (!issued) {
+        hit = gather_hit(A.g, r, z[1], *gc);
+        if (!hit) gather_issue(A.g, A.f, r, z[1], *gc);
+      }
     } else if constexpr (SPLIT) {
       gather_issue(A.g, A.f, r, z[1], gl);
     } else {
@@ -203,8 +206,12 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   const double hdt = 0.5 * dt;
   double k[6], acc[6], y[6], p, pacc, s, c;
   gc.pn = -1;
+  // the first stage's field loads go out before the angle's sine and cosine
+  // are computed, so that their latency overlaps that work
+  const bool pre = CACHE && GRID && qm != 0.0;
+  if (pre) gather_issue(A.g, A.f, z[0], z[1], gc);
   fsincos(z[1], s0, c0);
-  eval<GRID, false, CACHE, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc);
+  eval<GRID, false, CACHE, CACHE>(A, qm, z, *s0, *c0, k, &p, e0, &gc, pre);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     acc[i] = k[i];
@@ -587,18 +594,26 @@ __device__ __forceinline__ void load_z(const ParticleView& P, long k,
 template <bool GRID, bool EVOLVE, int WPS, bool CACHE = false>
 __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(WPS)))
 void k_push_explicit(PushArgs A) {
+  const ParticleView& P = A.p;
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // the state is loaded together with the flags, before the statistics are
+  // set up (one memory round trip before the first stage's field loads,
+  // overlapped with that set-up)
+  const bool inr = k < P.n;
+  double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, qm = 0.0;
+  uint8_t flg = 0;
+  if (inr) {
+    flg = P.flags[k];
+    load_z(P, k, z);
+    qm = (double)P.qm[k];
+  }
   __shared__ LocalStats ls;
   stats_init(ls);
   __syncthreads();
-  const ParticleView& P = A.p;
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool act = k < P.n && (P.flags[k] & F_ALIVE);
+  const bool act = inr && (flg & F_ALIVE);
   bool enq = false;
   double trial[6];
   if (act) {
-    double z[6];
-    load_z(P, k, z);
-    double qm = (double)P.qm[k];
     // without a grid each particle keeps its own time: the step is clipped
     // to the time left before t_end, and a particle at t_end stays
     double dt = A.dt, tk = 0.0;
