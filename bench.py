@@ -44,10 +44,11 @@ FLOP_SWITCH = 2 * FLOP_ENERGY + 3
 # hand counts of the kernel's formulation (shared samples, factored forms)
 FLOP_KERNEL_RK4_GRID = 4 * (89 + 76 + 93) + 90
 FLOP_KERNEL_WEIGHTS = 610
-# algorithmic HBM bytes per particle of the explicit push pass: state in/out
-# (2 x 48), q/m, flags, H0, herr in/out, iterations, old position + dphi,
-# new weights (three stored, the fourth is their complement) + cell
-BYTES_PUSH = 48 + 1 + 1 + 8 + 8 + 48 + 8 + 1 + 1 + 24 + 24 + 4
+# algorithmic HBM bytes per particle of the explicit push pass of a charged
+# particle under Hyb2: state in/out (2 x 48), q/m, flags in/out, herr out,
+# iterations, old position + dphi, new weights (three stored, the fourth is
+# their complement) + cell (a neutral particle also reads H0, Hyb1 herr)
+BYTES_PUSH = 48 + 1 + 1 + 48 + 1 + 8 + 1 + 24 + 24 + 4
 # deposit per particle: old/new weights (three each) and cells, q/m, w, dphi,
 # flags
 BYTES_DEPOSIT = 24 + 24 + 4 + 4 + 1 + 8 + 8 + 1
