@@ -124,26 +124,45 @@ __device__ __forceinline__ void dep_weights(const GridView& g, double r,
   dep_weights_at(g, r, th, st, ct, g.rn[p], g.rn[p + 1], g.stn[q], g.ctn[q], q, W);
 }
 
-// A node column known from a nearby gather: rn[pn] = rn0, rn[pn + 1] = rn1
-// (pn < 0: none).
+// The node cell of a nearby gather: rn[pn] = rn0, rn[pn + 1] = rn1 and
+// theta_node(qn) = tn0, theta_node(qn + 1) = tn1 (pn < 0: none; then the
+// other fields are undefined).
 struct ColumnHint {
   int pn;
   double rn0, rn1;
+  int qn;
+  double tn0, tn1;
 };
 
-// node cell (p, q) of (r, th) and its weights.  hint: the node column of a
-// nearby gather (the last RK4 stage); when r lies in it the radii come from
-// it, else the node values are loaded in one memory round trip (the FP32
-// radial estimate is checked against them).
+__device__ __forceinline__ ColumnHint column_hint(const GatherLoads& L) {
+  return ColumnHint{L.pn, L.rn0, L.rn1, L.qn, L.tn0, L.tn1};
+}
+
+// node cell (p, q) of (r, th) and its weights.  hint: the node cell of a
+// nearby gather (the last RK4 stage); when r lies in its column the radii
+// come from it, else the node values are loaded in one memory round trip
+// (the FP32 radial estimate is checked against them); when th lies in its
+// row, so do q and the row's angles.
 // The sin and cos of the cell's lower node angle follow from those of th by
 // the short series of sincos_near when the two are close, else from the
 // node tables.
 __device__ __forceinline__ void cell_and_weights(const GridView& g, double r, double th,
                                                  double st, double ct, int& p, int& q,
                                                  double* W,
-                                                 ColumnHint hint = ColumnHint{-1, 0.0, 0.0}) {
+                                                 ColumnHint hint = ColumnHint{-1, 0.0, 0.0,
+                                                                              -1, 0.0, 0.0}) {
   const int nr = g.nr;
-  q = theta_cell<false>(g, th, (th - g.th0) * g.inv_dth, g.nth + 1);
+  double tq, tq1;
+  if (hint.pn >= 0 && (hint.qn == 0 || th >= hint.tn0) &&
+      (hint.qn == g.nth - 1 || th < hint.tn1)) {
+    q = hint.qn;
+    tq = hint.tn0;
+    tq1 = hint.tn1;
+  } else {
+    q = theta_cell<false>(g, th, (th - g.th0) * g.inv_dth, g.nth + 1);
+    tq = theta_node(g, q);
+    tq1 = theta_node(g, q + 1);
+  }
   double r0, r1;
   if (hint.pn >= 0 && (hint.pn == 0 || r >= hint.rn0) && (hint.pn == nr - 1 || r < hint.rn1)) {
     p = hint.pn;
@@ -165,7 +184,6 @@ __device__ __forceinline__ void cell_and_weights(const GridView& g, double r, do
       r1 = g.rn[p + 1];
     }
   }
-  const double tq = theta_node(g, q);
   double sq, cq;
   if (fabs(tq - th) <= 0.01) {
     sincos_near(tq, th, st, ct, &sq, &cq);
@@ -173,7 +191,7 @@ __device__ __forceinline__ void cell_and_weights(const GridView& g, double r, do
     sq = g.stn[q];
     cq = g.ctn[q];
   }
-  dep_weights_at(g, r, th, st, ct, r0, r1, sq, cq, q, W);
+  dep_weights_box(g, r, th, st, ct, r0, r1, tq, tq1, sq, cq, W);
 }
 
 __device__ __forceinline__ void dep_weights(const GridView& g, double r,

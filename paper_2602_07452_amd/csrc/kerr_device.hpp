@@ -272,11 +272,26 @@ __device__ __forceinline__ void corner_loads(const FieldView& F, int nrn, int nr
   c[11] = ld2(a + nrh);
 }
 
+// bilinear form of the corners v_ij (i radial, j angular) as
+// c00 + fr c10 + ft (c01 + fr c11); lerp2 and the cached coefficients of
+// gather_coefs share this arithmetic, so both give the same bits
+struct Bilin {
+  double c00, c10, c01, c11;
+};
+
+__device__ __forceinline__ Bilin bilin(float2 r0, float2 r1) {
+  const double v00 = r0.x, v10 = r0.y, v01 = r1.x, v11 = r1.y;
+  return Bilin{v00, v10 - v00, v01 - v00, (v11 - v01) - (v10 - v00)};
+}
+
+__device__ __forceinline__ double bilin_eval(double c00, double c10, double c01, double c11,
+                                             double fr, double ft) {
+  return fma(ft, fma(fr, c11, c01), fma(fr, c10, c00));
+}
+
 __device__ __forceinline__ double lerp2(float2 r0, float2 r1, double fr, double ft) {
-  double v00 = r0.x, v10 = r0.y, v01 = r1.x, v11 = r1.y;
-  double b0 = v00 + fr * (v10 - v00);
-  double b1 = v01 + fr * (v11 - v01);
-  return b0 + ft * (b1 - b0);
+  const Bilin b = bilin(r0, r1);
+  return bilin_eval(b.c00, b.c10, b.c01, b.c11, fr, ft);
 }
 
 // D^i, B^i at (r, theta): sum_c w_c (sqrt(g) F)_c / sqrt(g)(x).  The theta
@@ -289,11 +304,13 @@ __device__ __forceinline__ double lerp2(float2 r0, float2 r1, double fr, double 
 struct GatherLoads {
   float2 c[12];
   double rn0, rn1, irn, rh0, rh1, irh;
+  // theta_node(qn), theta_node(qn + 1), theta_half(qn), theta_half(qh)
+  double tn0, tn1, thq, thh;
   int pn, ph, qn, qh;
-  // with gather_coefs: each component's corners in FP64 as the value at the
-  // lower radial corner and the radial difference, for the lower (v0, d0)
-  // and upper (v1, d1) corner row; the order of gather_interp's D, B
-  double v0[6], d0[6], v1[6], d1[6];
+  // with gather_coefs: each component's corners v_ij (i radial, j angular)
+  // in FP64 as the bilinear form's coefficients v00, v10 - v00, v01 - v00
+  // and (v11 - v01) - (v10 - v00); the order of gather_interp's D, B
+  double c00[6], c10[6], c01[6], c11[6];
 };
 
 __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView& F,
@@ -304,8 +321,12 @@ __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView&
   // the half-angle cell from the node cell: th lies in [theta_qn,
   // theta_qn+1), so its half cell is qn at or above theta_{qn+1/2} and
   // qn - 1 below (clamped to [0, nth - 2] like the search it replaces)
-  const int qh = th >= theta_half(g, L.qn) ? L.qn : L.qn - 1;
+  L.tn0 = theta_node(g, L.qn);
+  L.tn1 = theta_node(g, L.qn + 1);
+  L.thq = theta_half(g, L.qn);
+  const int qh = th >= L.thq ? L.qn : L.qn - 1;
   L.qh = qh < 0 ? 0 : (qh > g.nth - 2 ? g.nth - 2 : qh);
+  L.thh = L.qh == L.qn ? L.thq : theta_half(g, L.qh);
   const float lr = radial_coord(g, r);
   int pn = (int)floorf(lr), ph = (int)floorf(lr - 0.5f);
   L.pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
@@ -350,8 +371,8 @@ __device__ __forceinline__ void gather_interp(const GridView& g, double r, doubl
                                               double* B) {
   const float2* c = L.c;
   const double frn = clamp01((r - L.rn0) * L.irn), frh = clamp01((r - L.rh0) * L.irh);
-  const double ftn = clamp01((th - theta_node(g, L.qn)) * g.inv_dth);
-  const double fth = clamp01((th - theta_half(g, L.qh)) * g.inv_dth);
+  const double ftn = clamp01((th - L.tn0) * g.inv_dth);
+  const double fth = clamp01((th - L.thh) * g.inv_dth);
   D[0] = lerp2(c[0], c[1], frh, ftn) * isg;
   D[1] = lerp2(c[2], c[3], frn, fth) * isg;
   D[2] = lerp2(c[4], c[5], frn, ftn) * isg;
@@ -361,23 +382,21 @@ __device__ __forceinline__ void gather_interp(const GridView& g, double r, doubl
 }
 
 // the FP64 coefficients of the settled corners (once per loaded cell set;
-// interpolating from them gives exactly what gather_interp gives)
+// interpolating from them takes three FMAs per component and gives exactly
+// what gather_interp gives)
 __device__ __forceinline__ void gather_coefs(GatherLoads& L) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const double v00 = L.c[2 * j].x, v10 = L.c[2 * j].y;
-    const double v01 = L.c[2 * j + 1].x, v11 = L.c[2 * j + 1].y;
-    L.v0[j] = v00;
-    L.d0[j] = v10 - v00;
-    L.v1[j] = v01;
-    L.d1[j] = v11 - v01;
+    const Bilin b = bilin(L.c[2 * j], L.c[2 * j + 1]);
+    L.c00[j] = b.c00;
+    L.c10[j] = b.c10;
+    L.c01[j] = b.c01;
+    L.c11[j] = b.c11;
   }
 }
 
 __device__ __forceinline__ double lerp2c(const GatherLoads& L, int j, double fr, double ft) {
-  const double b0 = L.v0[j] + fr * L.d0[j];
-  const double b1 = L.v1[j] + fr * L.d1[j];
-  return b0 + ft * (b1 - b0);
+  return bilin_eval(L.c00[j], L.c10[j], L.c01[j], L.c11[j], fr, ft);
 }
 
 // gather_interp from the coefficients of gather_coefs
@@ -385,8 +404,8 @@ __device__ __forceinline__ void gather_interp_coefs(const GridView& g, double r,
                                                     double isg, const GatherLoads& L,
                                                     double* D, double* B) {
   const double frn = clamp01((r - L.rn0) * L.irn), frh = clamp01((r - L.rh0) * L.irh);
-  const double ftn = clamp01((th - theta_node(g, L.qn)) * g.inv_dth);
-  const double fth = clamp01((th - theta_half(g, L.qh)) * g.inv_dth);
+  const double ftn = clamp01((th - L.tn0) * g.inv_dth);
+  const double fth = clamp01((th - L.thh) * g.inv_dth);
   D[0] = lerp2c(L, 0, frh, ftn) * isg;
   D[1] = lerp2c(L, 1, frn, fth) * isg;
   D[2] = lerp2c(L, 2, frn, ftn) * isg;
@@ -402,22 +421,26 @@ __device__ __forceinline__ void gather_finish(const GridView& g, const FieldView
   gather_interp(g, r, th, isg, L, D, B);
 }
 
-// True when (r, th) lies in the cells whose corners L holds (L.pn < 0: none
-// yet), i.e. when a full gather would find exactly these cells: each cell is
-// the unique one with x_lo <= v < x_hi, open towards the clamped edges.
+// True only when (r, th) lies in the cells whose corners L holds (L.pn < 0:
+// none yet), i.e. when a full gather would find exactly these cells: each
+// cell is the unique one with x_lo <= v < x_hi, open towards the clamped
+// edges.  (A false answer is always safe: the caller gathers in full.)
 // Arithmetic only; lets an iteration whose point stays in its cells reuse
 // the corners it loaded.
 __device__ __forceinline__ bool gather_hit(const GridView& g, double r, double th,
                                            const GatherLoads& L) {
   const int nr = g.nr, nth = g.nth;
   if (L.pn < 0) return false;
-  const bool tn_ok = (L.qn == 0 || th >= theta_node(g, L.qn)) &&
-                     (L.qn == nth - 1 || th < theta_node(g, L.qn + 1));
-  int qh = th >= theta_half(g, L.qn) ? L.qn : L.qn - 1;
-  qh = qh < 0 ? 0 : (qh > nth - 2 ? nth - 2 : qh);
+  const bool tn_ok = (L.qn == 0 || th >= L.tn0) && (L.qn == nth - 1 || th < L.tn1);
+  // the half cell is qn at or above theta_half(qn), else qn - 1 (clamped).
+  // L.qh != L.qn only as L.qh = L.qn - 1, below theta_half(qn).  In the
+  // half cells next to the two axes, where the clamp acts, this test can
+  // answer false for a point of the same cells: it then takes the full
+  // gather, which finds them again
+  const bool th_ok = L.qh == L.qn ? th >= L.thq : th < L.thq;
   const bool rn_ok = (L.pn == 0 || r >= L.rn0) && (L.pn == nr - 1 || r < L.rn1);
   const bool rh_ok = (L.ph == 0 || r >= L.rh0) && (L.ph == nr - 2 || r < L.rh1);
-  return tn_ok && qh == L.qh && rn_ok && rh_ok;
+  return tn_ok && th_ok && rn_ok && rh_ok;
 }
 
 __device__ __forceinline__ void gather(const GridView& g, const FieldView& F,

@@ -99,14 +99,15 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
                                      GatherLoads* gc = nullptr, bool issued = false) {
   const double a = A.a, a2 = a * a, r = z[0], ur = z[3], ut = z[4], up = z[5];
   const double s2 = s * s, sc = s * c;
-  // one inverse square root y = (rho2 S)^(-1/2) gives alpha = sqrt(rho2 / S)
-  // = rho2 y, sqrt(gamma) = |sin| rho2 S y and its inverse, 1/S = rho2 y^2
-  // and 1/rho2 = S y^2
+  // one inverse square root w = (rho2 S sin^2)^(-1/2) = 1/sqrt(gamma) gives
+  // 1/sin^2 = rho2 S w^2, y = (rho2 S)^(-1/2) = |sin| w, alpha = sqrt(rho2 / S)
+  // = rho2 y, sqrt(gamma) = rho2 S sin^2 w, 1/S = rho2 y^2 and 1/rho2 = S y^2
   const double rho2 = r * r + a2 * c * c, S = rho2 + 2.0 * r, P = rho2 * S;
-  const double y = frsq(P), y2 = y * y, is2 = rcp(s2);
+  const double Q = P * s2, isg = frsq(Q), w2 = isg * isg;
+  const double is2 = P * w2, y2 = s2 * w2, y = fabs(s) * isg;
   const double irho2 = S * y2, iS = rho2 * y2;
   const double ixi = rho2 * iS, alpha = rho2 * y, betar = 2.0 * r * iS;
-  const double sg = fabs(s) * (P * y), isg = y * fabs(s) * is2;
+  const double sg = Q * isg;
   double D[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
   const bool charged = GRID && qm != 0.0;
   GatherLoads gl;
@@ -276,12 +277,12 @@ __device__ int imr(const PushArgs& A, double dt, double qm, const double* z, dou
     for (int i = 0; i < 6; ++i) zk[i] = zn[i];
     if (c) {
       *Wq = dt * p;
-      *col = ColumnHint{gc.pn, gc.rn0, gc.rn1};
+      *col = column_hint(gc);
       return k;
     }
   }
   *Wq = dt * p;
-  *col = ColumnHint{gc.pn, gc.rn0, gc.rn1};
+  *col = column_hint(gc);
   return -A.kmax;
 }
 
@@ -653,7 +654,7 @@ void k_push_explicit(PushArgs A) {
       }
       if (accept) {
         finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0, sn, cn,
-                         ColumnHint{gc.pn, gc.rn0, gc.rn1});
+                         column_hint(gc));
         if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
       } else {
         enq = true;
@@ -738,7 +739,7 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
         }
       }
       double Wq = 0.0, s0, c0;
-      ColumnHint col{-1, 0.0, 0.0};  // Picard: the last midpoint's node column
+      ColumnHint col{-1, 0.0, 0.0, -1, 0.0, 0.0};  // Picard: the last midpoint's node column
       fsincos(z[1], &s0, &c0);
       int it;
       if constexpr (NEWTON)
