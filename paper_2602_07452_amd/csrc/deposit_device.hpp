@@ -75,12 +75,23 @@ __device__ __forceinline__ void dep_weights_box(const GridView& g, double r, dou
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
       const double rr = i < 3 ? ra + i * h1r : (i == 3 ? r : r + (i - 3) * h2r);
-      double rho2 = rr * rr + C2;
-      double f = fsqrt_lo(rho2 * (rho2 + 2.0 * rr));
-      // a sample outside a sub-rectangle has weight 0 there (its term would
-      // add +0 exactly): only the nonzero terms are formed
-      if (i <= 3) rowa += ((i == 0 || i == 3) ? 0.5 : 1.0) * f;
-      if (i >= 3) rowb += ((i == 3 || i == 6) ? 0.5 : 1.0) * f;
+      const double rho2 = rr * rr + C2, X = rho2 * (rho2 + 2.0 * rr);
+      // sqrt(X) = s (1 + e / 2) to about 2^-48 relative, from the hardware
+      // estimate y of 1/sqrt(X), s = X y and e = 1 - s y (one Goldschmidt
+      // step; the weights end in FP32 sums).  A trapezoid weight w enters
+      // through the factor, w sqrt(X) = s (w + (w / 2) e), so that each
+      // term is one FMA.  A sample outside a sub-rectangle has weight 0
+      // there (its term would add +0 exactly): only the nonzero terms are
+      // formed
+      const double y = __builtin_amdgcn_rsq(X), sx = X * y, e = fma(-sx, y, 1.0);
+      if (i <= 3) {
+        const double w = (i == 0 || i == 3) ? 0.5 : 1.0;
+        rowa = fma(sx, fma(e, 0.5 * w, w), rowa);
+      }
+      if (i >= 3) {
+        const double w = (i == 3 || i == 6) ? 0.5 : 1.0;
+        rowb = fma(sx, fma(e, 0.5 * w, w), rowb);
+      }
     }
     if (j <= 3) {
       Vaa += wa_t * Sabs * rowa;  // [ra, r] x [ta, th]

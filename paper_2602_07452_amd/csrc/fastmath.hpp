@@ -31,16 +31,6 @@ __device__ __forceinline__ double fsqrt(double x) {
   return fma(h, r, s);
 }
 
-// sqrt(x) to about 2^-48 relative (the Goldschmidt step of fsqrt without
-// its final correction), for the many samples of the deposit weights, whose
-// sums are rounded to FP32 in the end
-__device__ __forceinline__ double fsqrt_lo(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double s = x * y, h = 0.5 * y;
-  double r = fma(-s, h, 0.5);
-  return fma(s, r, s);
-}
-
 // 1/sqrt(x) for finite x > 0 away from the denormal range: the hardware
 // estimate refined by two Newton steps y <- y + y (1/2 - (x/2) y^2)
 __device__ __forceinline__ double frsq(double x) {

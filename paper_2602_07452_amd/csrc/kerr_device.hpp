@@ -220,8 +220,10 @@ __device__ __forceinline__ int refine(const double* x, int n, double v, int p) {
   return p;
 }
 
+// f clamped to [0, 1]: two FP64 max/min instructions (a NaN comes out as 0;
+// a particle with a NaN coordinate is removed by its step anyway)
 __device__ __forceinline__ double clamp01(double f) {
-  return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+  return fmin(fmax(f, 0.0), 1.0);
 }
 
 // theta nodes of the uniform grid, bit-identical to the host tables
