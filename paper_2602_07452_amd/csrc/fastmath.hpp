@@ -6,14 +6,14 @@
 
 namespace grpic {
 
-// 1/x for finite, normal x: hardware estimate refined by two Newton steps
-// (each doubles the number of correct bits).
+// 1/x for finite, normal x: the hardware estimate y (relative error below
+// 2^-24 on this device) refined by one third-order step,
+// 1/x = y / (1 - e) = y (1 + e + e^2 + ...) with e = 1 - x y; the omitted
+// terms are below 2^-72 relative.
 __device__ __forceinline__ double frcp(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, fma(e, e, e), y);
 }
 
 // sqrt(x) for finite x > 0 away from the denormal range: the hardware
@@ -32,14 +32,13 @@ __device__ __forceinline__ double fsqrt(double x) {
 }
 
 // 1/sqrt(x) for finite x > 0 away from the denormal range: the hardware
-// estimate refined by two Newton steps y <- y + y (1/2 - (x/2) y^2)
+// estimate y (relative error below 2^-24) refined by one third-order step,
+// 1/sqrt(x) = y (1 - e)^(-1/2) = y (1 + e/2 + 3 e^2/8 + ...) with
+// e = 1 - x y^2; the omitted terms are below 2^-70 relative.
 __device__ __forceinline__ double frsq(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double r = fma(-h * y, y, 0.5);
-  y = fma(y, r, y);
-  r = fma(-h * y, y, 0.5);
-  return fma(y, r, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x, y * y, 1.0);
+  return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
 // sin and cos of x for |x| < 100 (polar angles here lie near [0, pi]):

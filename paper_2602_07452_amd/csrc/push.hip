@@ -237,7 +237,7 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   pacc += 2.0 * p;
   sincos_near(y[1], z[1], *s0, *c0, &s, &c);
   eval<GRID, false, CACHE, CACHE>(A, qm, y, s, c, k, &p, nullptr, &gc);
-  const double c6 = dt / 6.0;
+  const double c6 = dt * (1.0 / 6.0);
 #pragma unroll
   for (int i = 0; i < 6; ++i) out[i] = z[i] + c6 * (acc[i] + k[i]);
   *Wq = c6 * (pacc + p);
@@ -497,11 +497,12 @@ __device__ __forceinline__ double switch_value(const PushArgs& A, double qm,
   *sn = s;
   *cn = c;
   double e1 = energy_sc(A.a, zn, s, c);
+  // (the quotients by one refined reciprocal: within an ulp of the division)
   if (qm == 0.0) {
     const double h0 = *H0;
-    return fabs(e1 - h0) / fabs(h0);
+    return fabs(e1 - h0) * frcp(fabs(h0));
   }
-  return fabs(e1 - e0 - Wq) / fabs(e0);
+  return fabs(e1 - e0 - Wq) * frcp(fabs(e0));
 }
 
 // histogram bin b = floor(2 (log10 v + 30)) of an energy violation (a
