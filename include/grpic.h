@@ -114,7 +114,10 @@ enum grpic_level {
 /* ---- configuration ---------------------------------------------------- */
 typedef struct grpic_config {
   double a;              /* spin a_* in [0, 1)                              */
-  int nr, nth;           /* grid cells (ignored for GRPIC_FIELDS_NONE)      */
+  int nr, nth;           /* grid cells (ignored for GRPIC_FIELDS_NONE);     *
+                          * at least 2 and at most 2^22 - 2 each, with     *
+                          * (nr + 1)(nth + 1) <= 2^30 (else                *
+                          * GRPIC_E_INVALID)                               */
   double r_in, r_out;    /* radial extent of the grid                       */
   double theta0;         /* theta edges at theta0, pi - theta0 (Sec. 2.5)   */
   double dt;             /* time step (0 with a grid: half the Courant

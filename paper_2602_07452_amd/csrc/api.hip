@@ -85,7 +85,9 @@ void validate(const grpic_config& c) {
     bad("max_particles must lie in [0, 2^31)");
   if (c.field_mode != GRPIC_FIELDS_NONE) {
     if (c.nr < 2 || c.nth < 2) bad("grid needs at least 2 x 2 cells");
-    if ((long)(c.nr + 1) * (c.nth + 1) > (1L << 30)) bad("grid too large");
+    if ((long)(c.nr + 1) * (c.nth + 1) > (1L << 30) || c.nr > (1 << 22) - 2 ||
+        c.nth > (1 << 22) - 2)
+      bad("grid too large: (nr + 1)(nth + 1) must not exceed 2^30 and nr, nth 2^22 - 2");
     if (!(c.r_in > 0.0 && c.r_out > c.r_in)) bad("need 0 < r_in < r_out");
     if (!(c.theta0 > 0.0 && c.theta0 < 0.5 * kPi)) bad("theta0 must lie in (0, pi/2)");
     if (c.tile_r < 1 || c.tile_th < 1) bad("tile sizes must be positive");

@@ -249,29 +249,37 @@ __device__ __forceinline__ int theta_cell(const GridView& g, double th, double l
 }
 
 
-// the two adjacent values of a row and of the next row of each component
-__device__ __forceinline__ float2 ld2(const float* p) { return make_float2(p[0], p[1]); }
+// the two adjacent values at byte offset b of a field array.  Offsets are
+// 32-bit: a field array holds at most 2^30 values and a grid dimension is
+// below 2^22 cells (both checked when the context is created), so that row
+// offsets are 24-bit products and the loads take a scalar base address plus
+// a 32-bit vector offset.
+__device__ __forceinline__ float2 ld2(const float* base, uint32_t b) {
+  const float* p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + b);
+  return make_float2(p[0], p[1]);
+}
 
+// the two adjacent values of a row and of the next row of each component
 __device__ __forceinline__ void corner_loads(const FieldView& F, int nrn, int nrh, int pn,
                                              int ph, int qn, int qh, float2* c) {
-  const float* a = F.Dr + (long)qn * nrh + ph;
-  c[0] = ld2(a);
-  c[1] = ld2(a + nrh);
-  a = F.Dt + (long)qh * nrn + pn;
-  c[2] = ld2(a);
-  c[3] = ld2(a + nrn);
-  a = F.Dp + (long)qn * nrn + pn;
-  c[4] = ld2(a);
-  c[5] = ld2(a + nrn);
-  a = F.Br + (long)qh * nrn + pn;
-  c[6] = ld2(a);
-  c[7] = ld2(a + nrn);
-  a = F.Bt + (long)qn * nrh + ph;
-  c[8] = ld2(a);
-  c[9] = ld2(a + nrh);
-  a = F.Bp + (long)qh * nrh + ph;
-  c[10] = ld2(a);
-  c[11] = ld2(a + nrh);
+  const uint32_t sn = 4u * (uint32_t)nrn, sh = 4u * (uint32_t)nrh;  // row strides
+  const uint32_t bn = 4u * (uint32_t)pn, bh = 4u * (uint32_t)ph;
+  uint32_t b = __umul24((uint32_t)qn, sh) + bh;  // r-half columns, node rows
+  c[0] = ld2(F.Dr, b);
+  c[1] = ld2(F.Dr, b + sh);
+  c[8] = ld2(F.Bt, b);
+  c[9] = ld2(F.Bt, b + sh);
+  b = __umul24((uint32_t)qh, sn) + bn;  // node columns, theta-half rows
+  c[2] = ld2(F.Dt, b);
+  c[3] = ld2(F.Dt, b + sn);
+  c[6] = ld2(F.Br, b);
+  c[7] = ld2(F.Br, b + sn);
+  b = __umul24((uint32_t)qn, sn) + bn;  // node columns, node rows
+  c[4] = ld2(F.Dp, b);
+  c[5] = ld2(F.Dp, b + sn);
+  b = __umul24((uint32_t)qh, sh) + bh;  // r-half columns, theta-half rows
+  c[10] = ld2(F.Bp, b);
+  c[11] = ld2(F.Bp, b + sh);
 }
 
 // bilinear form of the corners v_ij (i radial, j angular) as
@@ -315,6 +323,23 @@ struct GatherLoads {
   double c00[6], c10[6], c01[6], c11[6];
 };
 
+// the radial node and half values bounding cells pn and ph and their
+// inverse widths (32-bit byte offsets, as in corner_loads)
+__device__ __forceinline__ double ldd(const double* base, uint32_t b) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + b);
+}
+
+__device__ __forceinline__ void radial_loads(const GridView& g, int pn, int ph,
+                                             GatherLoads& L) {
+  const uint32_t bn = 8u * (uint32_t)pn, bh = 8u * (uint32_t)ph;
+  L.rn0 = ldd(g.rn, bn);
+  L.rn1 = ldd(g.rn, bn + 8u);
+  L.irn = ldd(g.idrn, bn);
+  L.rh0 = ldd(g.rh, bh);
+  L.rh1 = ldd(g.rh, bh + 8u);
+  L.irh = ldd(g.idrh, bh);
+}
+
 __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView& F,
                                              double r, double th, GatherLoads& L) {
   const int nr = g.nr, nrn = nr + 1, nrh = nr;
@@ -334,12 +359,7 @@ __device__ __forceinline__ void gather_issue(const GridView& g, const FieldView&
   L.pn = pn < 0 ? 0 : (pn > nr - 1 ? nr - 1 : pn);
   L.ph = ph < 0 ? 0 : (ph > nr - 2 ? nr - 2 : ph);
   corner_loads(F, nrn, nrh, L.pn, L.ph, L.qn, L.qh, L.c);
-  L.rn0 = g.rn[L.pn];
-  L.rn1 = g.rn[L.pn + 1];
-  L.irn = g.idrn[L.pn];
-  L.rh0 = g.rh[L.ph];
-  L.rh1 = g.rh[L.ph + 1];
-  L.irh = g.idrh[L.ph];
+  radial_loads(g, L.pn, L.ph, L);
 }
 
 // Refine the estimated radial cells against the node values loaded with
@@ -358,12 +378,7 @@ __device__ __forceinline__ void gather_settle(const GridView& g, const FieldView
     L.pn = pn2;
     L.ph = ph2;
     corner_loads(F, nrn, nrh, pn2, ph2, L.qn, L.qh, L.c);
-    L.rn0 = g.rn[pn2];
-    L.rn1 = g.rn[pn2 + 1];
-    L.irn = g.idrn[pn2];
-    L.rh0 = g.rh[ph2];
-    L.rh1 = g.rh[ph2 + 1];
-    L.irh = g.idrh[ph2];
+    radial_loads(g, pn2, ph2, L);
   }
 }
 

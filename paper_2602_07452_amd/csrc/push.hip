@@ -514,12 +514,42 @@ __device__ __forceinline__ int herr_bin(double v) {
   return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
 }
 
+// A particle array element: at(p, k) with a 64-bit index k, or with an
+// Off32 index, whose byte offsets are 32-bit (particle counts below 2^28,
+// so below 2^31 bytes): the explicit pass then addresses every array as a
+// scalar base plus one 32-bit lane offset per element size, instead of a
+// 64-bit address sum per array.
+struct Off32 {
+  uint32_t i;
+};
+
+template <class T>
+__device__ __forceinline__ T& at(T* p, long k) {
+  return p[k];
+}
+
+template <class Ix>
+__device__ __forceinline__ Ix make_ix(long k);
+template <>
+__device__ __forceinline__ long make_ix<long>(long k) {
+  return k;
+}
+template <>
+__device__ __forceinline__ Off32 make_ix<Off32>(long k) {
+  return Off32{(uint32_t)k};
+}
+
+template <class T>
+__device__ __forceinline__ T& at(T* p, Off32 k) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + k.i * (uint32_t)sizeof(T));
+}
+
 // write the step result, apply the particle boundary conditions and (for a
 // deposit) store the old position and the weights of the new one
 // s0, c0: sin, cos of z[1]
-template <bool EVOLVE>
+template <bool EVOLVE, class Ix>
 // sn, cn: sin, cos of out[1] as pushed; hint: the last stage's node column
-__device__ void finalize(const PushArgs& A, long k, const double* z,
+__device__ void finalize(const PushArgs& A, Ix k, const double* z,
                          double* out, double herr, int iters, uint8_t fl,
                          LocalStats& ls, double s0, double c0, double sn, double cn,
                          ColumnHint hint) {
@@ -548,15 +578,15 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
     }
   }
   const bool moved = (fl & F_REFLECTED) != 0;
-  P.r[k] = out[0];
-  P.th[k] = out[1];
-  P.ph[k] = out[2];
-  P.ur[k] = out[3];
-  P.uth[k] = out[4];
-  P.uph[k] = out[5];
-  P.herr[k] = herr;
-  P.flags[k] = fl;
-  P.iters[k] = (uint8_t)(iters < 255 ? iters : 255);  // a restart can take 2 kmax
+  at(P.r, k) = out[0];
+  at(P.th, k) = out[1];
+  at(P.ph, k) = out[2];
+  at(P.ur, k) = out[3];
+  at(P.uth, k) = out[4];
+  at(P.uph, k) = out[5];
+  at(P.herr, k) = herr;
+  at(P.flags, k) = fl;
+  at(P.iters, k) = (uint8_t)(iters < 255 ? iters : 255);  // a restart can take 2 kmax
   if (fl & F_ALIVE) {
     atomicAdd(&ls.alive, 1u);
     atomicAdd(&ls.herr_hist[herr_bin(herr)], 1u);
@@ -567,47 +597,49 @@ __device__ void finalize(const PushArgs& A, long k, const double* z,
   }
   if (fl & F_NOCONV) atomicAdd(&ls.noconv, 1u);
   if (EVOLVE) {
-    P.r_old[k] = z[0];
-    P.th_old[k] = z[1];
-    P.dphi[k] = out[2] - z[2];
+    at(P.r_old, k) = z[0];
+    at(P.th_old, k) = z[1];
+    at(P.dphi, k) = out[2] - z[2];
     if (fl & F_ALIVE) {
       int p, q;
       double W[4], st = sn, ct = cn;
       if (moved) sincos_near(out[1], z[1], s0, c0, &st, &ct);
       cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W, hint);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) P.Wn[c][k] = W[c];
-      P.celln[k] = q * A.g.nr + p;
+      for (int c = 1; c < 4; ++c) at(P.Wn[c], k) = W[c];
+      at(P.celln, k) = q * A.g.nr + p;
     }
   }
 }
 
-__device__ __forceinline__ void load_z(const ParticleView& P, long k,
-                                       double* z) {
-  z[0] = P.r[k];
-  z[1] = P.th[k];
-  z[2] = P.ph[k];
-  z[3] = P.ur[k];
-  z[4] = P.uth[k];
-  z[5] = P.uph[k];
+template <class Ix>
+__device__ __forceinline__ void load_z(const ParticleView& P, Ix k, double* z) {
+  z[0] = at(P.r, k);
+  z[1] = at(P.th, k);
+  z[2] = at(P.ph, k);
+  z[3] = at(P.ur, k);
+  z[4] = at(P.uth, k);
+  z[5] = at(P.uph, k);
 }
 
 // ------------------------------------------------------- explicit pass
-template <bool GRID, bool EVOLVE, int WPS, bool CACHE = false>
+template <bool GRID, bool EVOLVE, int WPS, bool CACHE = false, bool OFF32 = false>
 __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(WPS)))
 void k_push_explicit(PushArgs A) {
   const ParticleView& P = A.p;
-  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long kg = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  using Ix = typename std::conditional<OFF32, Off32, long>::type;
+  const Ix k = make_ix<Ix>(kg);
   // the state is loaded together with the flags, before the statistics are
   // set up (one memory round trip before the first stage's field loads,
   // overlapped with that set-up)
-  const bool inr = k < P.n;
+  const bool inr = kg < P.n;
   double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, qm = 0.0;
   uint8_t flg = 0;
   if (inr) {
-    flg = P.flags[k];
+    flg = at(P.flags, k);
     load_z(P, k, z);
-    qm = (double)P.qm[k];
+    qm = (double)at(P.qm, k);
   }
   __shared__ LocalStats ls;
   stats_init(ls);
@@ -621,7 +653,7 @@ void k_push_explicit(PushArgs A) {
     double dt = A.dt, tk = 0.0;
     bool frozen = false, ends = false;
     if constexpr (!GRID) {
-      tk = P.t[k];
+      tk = at(P.t, k);
       if (A.t_end > 0.0) {
         double left = A.t_end - tk;
         if (!(left > 0.0)) {
@@ -633,10 +665,10 @@ void k_push_explicit(PushArgs A) {
       }
     }
     if (frozen) {
-      P.flags[k] = F_ALIVE;
-      P.iters[k] = 0;
+      at(P.flags, k) = F_ALIVE;
+      at(P.iters, k) = 0;
       atomicAdd(&ls.alive, 1u);
-      atomicAdd(&ls.herr_hist[herr_bin(P.herr[k])], 1u);
+      atomicAdd(&ls.herr_hist[herr_bin(at(P.herr, k))], 1u);
     } else if (A.pusher == GRPIC_PUSH_IMR || A.pusher == GRPIC_PUSH_HAM) {
       enq = true;
 #pragma unroll
@@ -645,18 +677,18 @@ void k_push_explicit(PushArgs A) {
       double Wq, e0, s0, c0, sn, cn;
       GatherLoads gc;
       rk4<GRID, CACHE && GRID>(A, dt, qm, z, trial, &Wq, &e0, &s0, &c0, gc);
-      double v = switch_value(A, qm, P.H0 + k, e0, trial, Wq, z[1], s0, c0, &sn, &cn);
+      double v = switch_value(A, qm, &at(P.H0, k), e0, trial, Wq, z[1], s0, c0, &sn, &cn);
       bool accept = true;
       if (A.pusher == GRPIC_PUSH_HYB2) {
         accept = v < A.thr;
       } else if (A.pusher == GRPIC_PUSH_HYB1) {
-        double prev = P.herr[k];
+        double prev = at(P.herr, k);
         accept = (v - prev) / (dt * fmax(prev, 0x1p-52)) < A.thr;
       }
       if (accept) {
         finalize<EVOLVE>(A, k, z, trial, v, 0, F_ALIVE, ls, s0, c0, sn, cn,
                          column_hint(gc));
-        if constexpr (!GRID) P.t[k] = ends ? A.t_end : tk + dt;
+        if constexpr (!GRID) at(P.t, k) = ends ? A.t_end : tk + dt;
       } else {
         enq = true;
       }
@@ -683,7 +715,7 @@ void k_push_explicit(PushArgs A) {
   if (enq) {
     unsigned slot = seg * A.seg_cap + s_base + s_off[wave] +
                     (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-    A.queue[slot] = (int)k;
+    A.queue[slot] = (int)kg;
     // first iterate (RK4 result; the base of the learned guess in the hybrid)
     if (A.use_gz && (A.guess == GRPIC_GUESS_RK4 || A.pusher == GRPIC_PUSH_HYB1 ||
                      A.pusher == GRPIC_PUSH_HYB2)) {
@@ -843,6 +875,9 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   if (c->cfg.push_waves_per_simd >= 4)
     hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE, 4>), dim3(grid_for(c->n, block)),
                        dim3(block), 0, c->stream, A);
+  else if (c->n < (1L << 28))  // 32-bit byte offsets into the particle arrays
+    hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE, 1, true, true>),
+                       dim3(grid_for(c->n, block)), dim3(block), 0, c->stream, A);
   else
     hipLaunchKernelGGL((k_push_explicit<GRID, EVOLVE, 1, true>), dim3(grid_for(c->n, block)),
                        dim3(block), 0, c->stream, A);

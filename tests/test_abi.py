@@ -59,6 +59,16 @@ def test_invalid_config_is_rejected_without_gpu():
         G.Context(cfg)
 
 
+def test_grids_beyond_the_index_limits_are_rejected_without_gpu():
+    """Field arrays are indexed with 32-bit byte offsets: (nr + 1)(nth + 1)
+    may not exceed 2^30 and neither dimension 2^22 - 2."""
+    for nr, nth in ((1 << 22) - 1, 2), (2, (1 << 22) - 1), (1 << 15, 1 << 15):
+        cfg = G.config_default(a=0.5, nr=nr, nth=nth, r_in=1.0, r_out=10.0,
+                               field_mode=G.FIELDS_STATIC)
+        with pytest.raises(G.GrpicError, match="grid too large"):
+            G.Context(cfg)
+
+
 def test_paper_deposit_and_cleaning_need_evolving_fields():
     for kw in (dict(deposit_mode=G.DEPOSIT_PAPER), dict(clean_every=25),
                dict(deposit_mode=7, field_mode=G.FIELDS_EVOLVE)):
