@@ -325,15 +325,19 @@ int grpic_use_graph(grpic_ctx *ctx, int enable);
 #define GRPIC_HIST_BINS 64
 typedef struct grpic_diag {
   long steps;            /* steps taken since load                          */
-  long alive;            /* particles alive                                 */
+  long alive;            /* particles alive (counted from the particle
+                            arrays when the diagnostics are read)          */
   long removed;          /* removed since load                              */
   long implicit_steps;   /* particle-steps taken implicitly (cumulative)    */
   long noconv;           /* implicit solves that hit kmax (cumulative)      */
   long reflected;        /* pole reflections (cumulative)                   */
   long iter_hist[GRPIC_HIST_BINS]; /* implicit iteration counts             */
   long herr_hist[GRPIC_HIST_BINS]; /* log10 energy-violation bins of the
-                                      last step: bin b holds values in
-                                      [10^(b/2-30), 10^((b+1)/2-30))       */
+                                      alive particles, the values their
+                                      last step wrote (0 before the
+                                      first): bin b holds values in
+                                      [10^(b/2-30), 10^((b+1)/2-30)), bin
+                                      0 also those below 1e-30            */
   long deposit_fallback; /* deposit blocks whose node box did not fit the
                             on-chip bins (cumulative)                      */
   long nonfinite;        /* particles removed for a non-finite state

@@ -1062,21 +1062,20 @@ int grpic_get_diagnostics(grpic_ctx* c, grpic_diag* out) {
     if (!out) throw Error(GRPIC_E_INVALID, "null pointer");
     std::unique_ptr<Stats> sp(new Stats);
     const Stats& s = *sp;
+    launch_census(c);
     GRPIC_HIP(hipStreamSynchronize(c->stream));
     GRPIC_HIP(hipMemcpy(sp.get(), c->stats, sizeof(Stats), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     out->steps = c->steps;
+    out->alive = (long)s.census[0];
+    for (int i = 0; i < GRPIC_HIST_BINS; ++i) out->herr_hist[i] = (long)s.census[1 + i];
     for (const StatRep& r : s.rep) {
-      out->alive += (long)r.alive;
       out->removed += (long)r.removed;
       out->implicit_steps += (long)r.implicit_steps;
       out->noconv += (long)r.noconv;
       out->reflected += (long)r.reflected;
       out->nonfinite += (long)r.nonfinite;
-      for (int i = 0; i < GRPIC_HIST_BINS; ++i) {
-        out->iter_hist[i] += (long)r.iter_hist[i];
-        out->herr_hist[i] += (long)r.herr_hist[i];
-      }
+      for (int i = 0; i < GRPIC_HIST_BINS; ++i) out->iter_hist[i] += (long)r.iter_hist[i];
     }
     out->deposit_fallback = (long)s.deposit_fallback;
     out->deposit_outside = (long)s.deposit_outside;

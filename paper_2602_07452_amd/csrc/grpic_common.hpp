@@ -42,15 +42,18 @@ constexpr int kQueueSegs = 256;  // the implicit queue is split in segments
 constexpr int kPushBlock = 64;   // threads per block of the explicit push
 
 struct StatRep {
-  unsigned long long implicit_steps, noconv, removed, reflected, alive;
+  unsigned long long implicit_steps, noconv, removed, reflected;
   unsigned long long iter_hist[kHistBins];
-  unsigned long long herr_hist[kHistBins];
   unsigned long long nonfinite;
-  unsigned long long pad[2];
+  unsigned long long pad[3];
 };
 
 struct Stats {
   StatRep rep[kStatReps];
+  // alive particles and the histogram of their energy violations, counted
+  // from the particle arrays when the diagnostics are read (census[0]:
+  // alive, census[1 + b]: bin b)
+  unsigned long long census[1 + kHistBins];
   unsigned int seg_count[kQueueSegs];  // entries in each queue segment
   unsigned int deposit_fallback; // deposit segments that used global atomics
   unsigned int cross_count;      // crossing moves queued by the deposit
@@ -192,6 +195,7 @@ void launch_fields_step_pre(grpic_ctx* c);   // sub-steps 1-4
 void launch_fields_step_post(grpic_ctx* c);  // sub-steps 7-10
 void launch_fill(grpic_ctx* c, void* p, size_t bytes);
 void launch_push(grpic_ctx* c);              // sub-step 5
+void launch_census(grpic_ctx* c);            // alive count, energy histogram
 void launch_deposit(grpic_ctx* c);           // sub-step 6
 void launch_deposit_initial(grpic_ctx* c);
 void launch_init_particles(grpic_ctx* c, const grpic_init_spec* s,

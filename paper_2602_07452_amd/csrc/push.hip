@@ -41,35 +41,65 @@ struct PushArgs {
   CollectView col;  // training-sample collection (col.T == nullptr: off)
 };
 
+// Step statistics.  Alive particles and their energy-violation histogram
+// are not counted here: the diagnostics count them from the particle
+// arrays when they are read (k_census).  The rest are counted by finalize
+// through a sink: the block's LDS counters where lanes finalise many
+// particles (the implicit pass), or direct global atomics for the rare
+// events of the explicit pass (removal, reflection), which so needs no LDS
+// counters, no barrier and no flush.
 struct LocalStats {
-  unsigned int herr_hist[kHistBins];
   unsigned int iter_hist[kHistBins];
-  unsigned int implicit_steps, noconv, removed, reflected, alive, nonfinite;
+  unsigned int implicit_steps, noconv, removed, reflected, nonfinite;
 };
 
 __device__ __forceinline__ void stats_init(LocalStats& s) {
-  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) {
-    s.herr_hist[i] = 0;
-    s.iter_hist[i] = 0;
-  }
-  if (threadIdx.x == 0)
-    s.implicit_steps = s.noconv = s.removed = s.reflected = s.alive = s.nonfinite = 0;
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) s.iter_hist[i] = 0;
+  if (threadIdx.x == 0) s.implicit_steps = s.noconv = s.removed = s.reflected = s.nonfinite = 0;
 }
 
 __device__ __forceinline__ void stats_flush(const LocalStats& s, Stats* st) {
   StatRep* g = &st->rep[blockIdx.x % kStatReps];
-  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) {
-    if (s.herr_hist[i]) atomicAdd(&g->herr_hist[i], (unsigned long long)s.herr_hist[i]);
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
     if (s.iter_hist[i]) atomicAdd(&g->iter_hist[i], (unsigned long long)s.iter_hist[i]);
-  }
   if (threadIdx.x == 0) {
     if (s.implicit_steps) atomicAdd(&g->implicit_steps, (unsigned long long)s.implicit_steps);
     if (s.noconv) atomicAdd(&g->noconv, (unsigned long long)s.noconv);
     if (s.removed) atomicAdd(&g->removed, (unsigned long long)s.removed);
     if (s.reflected) atomicAdd(&g->reflected, (unsigned long long)s.reflected);
-    if (s.alive) atomicAdd(&g->alive, (unsigned long long)s.alive);
     if (s.nonfinite) atomicAdd(&g->nonfinite, (unsigned long long)s.nonfinite);
   }
+}
+
+// what finalize counts, from the flags it wrote
+__device__ __forceinline__ void record(LocalStats& s, uint8_t fl, int iters) {
+  if (fl & F_REMOVED) {
+    atomicAdd(&s.removed, 1u);
+    if (fl & F_NONFINITE) atomicAdd(&s.nonfinite, 1u);
+  }
+  if (fl & F_REFLECTED) atomicAdd(&s.reflected, 1u);
+  if (fl & F_IMPLICIT) {
+    atomicAdd(&s.implicit_steps, 1u);
+    atomicAdd(&s.iter_hist[iters < kHistBins ? iters : kHistBins - 1], 1u);
+  }
+  if (fl & F_NOCONV) atomicAdd(&s.noconv, 1u);
+}
+
+struct GlobalStats {
+  StatRep* g;  // the block's replica
+};
+
+__device__ __forceinline__ void record(GlobalStats& s, uint8_t fl, int iters) {
+  if (fl & F_REMOVED) {
+    atomicAdd(&s.g->removed, 1ull);
+    if (fl & F_NONFINITE) atomicAdd(&s.g->nonfinite, 1ull);
+  }
+  if (fl & F_REFLECTED) atomicAdd(&s.g->reflected, 1ull);
+  if (fl & F_IMPLICIT) {
+    atomicAdd(&s.g->implicit_steps, 1ull);
+    atomicAdd(&s.g->iter_hist[iters < kHistBins ? iters : kHistBins - 1], 1ull);
+  }
+  if (fl & F_NOCONV) atomicAdd(&s.g->noconv, 1ull);
 }
 
 // --------------------------------------------------------------- F(z)
@@ -547,11 +577,11 @@ __device__ __forceinline__ T& at(T* p, Off32 k) {
 // write the step result, apply the particle boundary conditions and (for a
 // deposit) store the old position and the weights of the new one
 // s0, c0: sin, cos of z[1]
-template <bool EVOLVE, class Ix>
+template <bool EVOLVE, class Ix, class Sink>
 // sn, cn: sin, cos of out[1] as pushed; hint: the last stage's node column
 __device__ void finalize(const PushArgs& A, Ix k, const double* z,
                          double* out, double herr, int iters, uint8_t fl,
-                         LocalStats& ls, double s0, double c0, double sn, double cn,
+                         Sink& ls, double s0, double c0, double sn, double cn,
                          ColumnHint hint) {
   const ParticleView& P = A.p;
   bool finite = true;
@@ -559,22 +589,17 @@ __device__ void finalize(const PushArgs& A, Ix k, const double* z,
   for (int i = 0; i < 6; ++i) finite = finite && isfinite(out[i]);
   if (!finite) {  // a state that is no number: taken out of the run
     fl = F_REMOVED | F_NONFINITE;
-    atomicAdd(&ls.removed, 1u);
-    atomicAdd(&ls.nonfinite, 1u);
   } else if (out[0] < A.r_min || out[0] > A.r_max) {
     fl = F_REMOVED;
-    atomicAdd(&ls.removed, 1u);
   } else if (A.reflect) {
     if (out[1] < A.th_lo) {
       out[1] = 2.0 * A.th_lo - out[1];
       out[4] = -out[4];
       fl |= F_REFLECTED;
-      atomicAdd(&ls.reflected, 1u);
     } else if (out[1] > A.th_hi) {
       out[1] = 2.0 * A.th_hi - out[1];
       out[4] = -out[4];
       fl |= F_REFLECTED;
-      atomicAdd(&ls.reflected, 1u);
     }
   }
   const bool moved = (fl & F_REFLECTED) != 0;
@@ -587,15 +612,7 @@ __device__ void finalize(const PushArgs& A, Ix k, const double* z,
   at(P.herr, k) = herr;
   at(P.flags, k) = fl;
   at(P.iters, k) = (uint8_t)(iters < 255 ? iters : 255);  // a restart can take 2 kmax
-  if (fl & F_ALIVE) {
-    atomicAdd(&ls.alive, 1u);
-    atomicAdd(&ls.herr_hist[herr_bin(herr)], 1u);
-  }
-  if (fl & F_IMPLICIT) {
-    atomicAdd(&ls.implicit_steps, 1u);
-    atomicAdd(&ls.iter_hist[iters < kHistBins ? iters : kHistBins - 1], 1u);
-  }
-  if (fl & F_NOCONV) atomicAdd(&ls.noconv, 1u);
+  record(ls, fl, iters);
   if (EVOLVE) {
     at(P.r_old, k) = z[0];
     at(P.th_old, k) = z[1];
@@ -641,9 +658,7 @@ void k_push_explicit(PushArgs A) {
     load_z(P, k, z);
     qm = (double)at(P.qm, k);
   }
-  __shared__ LocalStats ls;
-  stats_init(ls);
-  __syncthreads();
+  GlobalStats ls{&A.st->rep[blockIdx.x % kStatReps]};
   const bool act = inr && (flg & F_ALIVE);
   bool enq = false;
   double trial[6];
@@ -667,8 +682,6 @@ void k_push_explicit(PushArgs A) {
     if (frozen) {
       at(P.flags, k) = F_ALIVE;
       at(P.iters, k) = 0;
-      atomicAdd(&ls.alive, 1u);
-      atomicAdd(&ls.herr_hist[herr_bin(at(P.herr, k))], 1u);
     } else if (A.pusher == GRPIC_PUSH_IMR || A.pusher == GRPIC_PUSH_HAM) {
       enq = true;
 #pragma unroll
@@ -723,7 +736,6 @@ void k_push_explicit(PushArgs A) {
       for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
     }
   }
-  stats_flush(ls, A.st);
 }
 
 // ------------------------------------------------------- implicit pass
@@ -818,14 +830,28 @@ __global__ __launch_bounds__(256) void k_push_implicit(PushArgs A) {
   stats_flush(ls, A.st);
 }
 
+// alive particles and the histogram of the energy violations their last
+// step wrote (census[0]: alive, census[1 + b]: bin b of herr_bin)
+__global__ __launch_bounds__(256) void k_census(ParticleView P, unsigned long long* census) {
+  __shared__ unsigned int h[1 + kHistBins];
+  for (int i = threadIdx.x; i <= kHistBins; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < P.n; k += stride) {
+    if (P.flags[k] & F_ALIVE) {
+      atomicAdd(&h[0], 1u);
+      atomicAdd(&h[1 + herr_bin(P.herr[k])], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= kHistBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&census[i], (unsigned long long)h[i]);
+}
+
 // per-step counters back to zero (cumulative counters are kept)
 __global__ void k_reset_step(Stats* st) {
   const int t = threadIdx.x;
   for (int i = t; i < kQueueSegs; i += blockDim.x) st->seg_count[i] = 0;
-  for (int r = 0; r < kStatReps; ++r) {
-    for (int i = t; i < kHistBins; i += blockDim.x) st->rep[r].herr_hist[i] = 0;
-    if (t == 0) st->rep[r].alive = 0;
-  }
 }
 
 static PushArgs make_args(grpic_ctx* c) {
@@ -913,6 +939,19 @@ static void push_impl(grpic_ctx* c, const PushArgs& A) {
   GRPIC_HIP(hipGetLastError());
   time_end(c, GRPIC_K_IMPLICIT, ev);
   if (collect) mlp_collect_advance(c);
+}
+
+void launch_census(grpic_ctx* c) {
+  launch_fill(c, c->stats->census, sizeof(c->stats->census));
+  if (c->n == 0) return;
+  // a few blocks per CU; each block's LDS counts stay far below 2^32
+  long blocks = (c->n + 255) / 256;
+  if (blocks > 8L * c->num_cus) blocks = 8L * c->num_cus;
+  ParticleView P = c->pv;
+  P.n = c->n;
+  hipLaunchKernelGGL(k_census, dim3((unsigned)blocks), dim3(256), 0, c->stream, P,
+                     c->stats->census);
+  GRPIC_HIP(hipGetLastError());
 }
 
 void launch_push(grpic_ctx* c) {

@@ -81,3 +81,42 @@ def test_pbz_time_series_matches_oracle():
     err = np.abs(sg - so).max(axis=1) / scale
     print(f"P_BZ(r) time series: max relative difference {err.max():.2e} over {steps} steps")
     assert err.max() < 1e-4
+
+
+def _herr_bins(v):
+    """Host bins of energy violations, floor(2 (log10 v + 30)) clamped to
+    [0, 63]; 0 for v < 1e-30 or NaN."""
+    v = np.asarray(v, np.float64)
+    ok = v >= 1e-30
+    b = np.zeros(v.shape, np.int64)
+    b[ok] = np.floor(2.0 * (np.log10(np.minimum(v[ok], 1e30)) + 30.0)).astype(np.int64)
+    return np.clip(b, 0, G.HIST_BINS - 1)
+
+
+def test_particle_census_matches_the_particle_arrays():
+    """The alive count and the energy-violation histogram of the diagnostics
+    are those of the particle arrays after the last step (a hot plasma up to
+    the outer edge, so that particles are removed and some steps are taken
+    implicitly).  The device bins with an FP32 logarithm: a value within
+    1e-6 of a bin edge may land on either side."""
+    cfg = _cfg(n=4096)
+    with G.Context(cfg) as ctx:
+        ctx.set_fields_wald(1.0)
+        ctx.init_particles(G.INIT_SHELL_MJ, cfg.max_particles, SEED + 81, rplus(cfg.a), 19.9,
+                           cfg.theta0, np.pi - cfg.theta0, 1.0, w=2e-3)
+        d = ctx.diagnostics()
+        assert d["alive"] == cfg.max_particles and d["herr_hist"][0] == cfg.max_particles
+        for _ in range(3):
+            ctx.step(4)
+            d = ctx.diagnostics()
+            P = ctx.get_particles()
+            alive = (P["flags"] & G.FLAG_ALIVE) != 0
+            assert d["alive"] == int(alive.sum())
+            v = P["herr"][alive]
+            lo, hi = _herr_bins(v * (1.0 - 1e-6)), _herr_bins(v * (1.0 + 1e-6))
+            sure = np.bincount(lo[lo == hi], minlength=G.HIST_BINS)
+            h = d["herr_hist"]
+            assert h.sum() == alive.sum()
+            assert np.all(h >= sure) and (h - sure).sum() == int((lo != hi).sum())
+        assert d["removed"] > 0 and d["implicit_steps"] > 0
+        assert alive.sum() < cfg.max_particles
