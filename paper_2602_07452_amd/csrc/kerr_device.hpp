@@ -316,6 +316,9 @@ struct GatherLoads {
   double rn0, rn1, irn, rh0, rh1, irh;
   // theta_node(qn), theta_node(qn + 1), theta_half(qn), theta_half(qh)
   double tn0, tn1, thq, thh;
+  // with gather_bounds: the point lies in all four cells (node and half, in
+  // r and in theta) exactly when rlo <= r < rhi and tlo <= th < thi
+  double rlo, rhi, tlo, thi;
   int pn, ph, qn, qh;
   // with gather_coefs: each component's corners v_ij (i radial, j angular)
   // in FP64 as the bilinear form's coefficients v00, v10 - v00, v01 - v00
@@ -438,6 +441,24 @@ __device__ __forceinline__ void gather_finish(const GridView& g, const FieldView
   gather_interp(g, r, th, isg, L, D, B);
 }
 
+// the hit bounds of the settled cells: each cell is the unique one with
+// x_lo <= v < x_hi, open towards the clamped grid edges (an infinite bound
+// there); the half theta cell is qn at or above theta_half(qn), else
+// qn - 1 (L.qh != L.qn only as L.qh = L.qn - 1).  In the half theta cells
+// next to the two axes, where the clamp acts, a point of the same cells can
+// fall outside these bounds: it then takes the full gather, which finds
+// them again.
+__device__ __forceinline__ void gather_bounds(const GridView& g, GatherLoads& L) {
+  const double inf = __builtin_huge_val();
+  const double rnl = L.pn == 0 ? -inf : L.rn0, rnh = L.pn == g.nr - 1 ? inf : L.rn1;
+  const double rhl = L.ph == 0 ? -inf : L.rh0, rhh = L.ph == g.nr - 2 ? inf : L.rh1;
+  L.rlo = fmax(rnl, rhl);
+  L.rhi = fmin(rnh, rhh);
+  const double tnl = L.qn == 0 ? -inf : L.tn0, tnh = L.qn == g.nth - 1 ? inf : L.tn1;
+  L.tlo = L.qh == L.qn ? fmax(tnl, L.thq) : tnl;
+  L.thi = L.qh == L.qn ? tnh : fmin(tnh, L.thq);
+}
+
 // True only when (r, th) lies in the cells whose corners L holds (L.pn < 0:
 // none yet), i.e. when a full gather would find exactly these cells: each
 // cell is the unique one with x_lo <= v < x_hi, open towards the clamped
@@ -446,18 +467,7 @@ __device__ __forceinline__ void gather_finish(const GridView& g, const FieldView
 // the corners it loaded.
 __device__ __forceinline__ bool gather_hit(const GridView& g, double r, double th,
                                            const GatherLoads& L) {
-  const int nr = g.nr, nth = g.nth;
-  if (L.pn < 0) return false;
-  const bool tn_ok = (L.qn == 0 || th >= L.tn0) && (L.qn == nth - 1 || th < L.tn1);
-  // the half cell is qn at or above theta_half(qn), else qn - 1 (clamped).
-  // L.qh != L.qn only as L.qh = L.qn - 1, below theta_half(qn).  In the
-  // half cells next to the two axes, where the clamp acts, this test can
-  // answer false for a point of the same cells: it then takes the full
-  // gather, which finds them again
-  const bool th_ok = L.qh == L.qn ? th >= L.thq : th < L.thq;
-  const bool rn_ok = (L.pn == 0 || r >= L.rn0) && (L.pn == nr - 1 || r < L.rn1);
-  const bool rh_ok = (L.ph == 0 || r >= L.rh0) && (L.ph == nr - 2 || r < L.rh1);
-  return tn_ok && th_ok && rn_ok && rh_ok;
+  return L.pn >= 0 && r >= L.rlo && r < L.rhi && th >= L.tlo && th < L.thi;
 }
 
 __device__ __forceinline__ void gather(const GridView& g, const FieldView& F,

@@ -182,10 +182,14 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
         if (!hit) {
           gather_settle(A.g, A.f, r, *gc);
           gather_coefs(*gc);
+          gather_bounds(A.g, *gc);
         }
         gather_interp_coefs(A.g, r, z[1], isg, *gc, D, B);
       } else {
-        if (!hit) gather_settle(A.g, A.f, r, *gc);
+        if (!hit) {
+          gather_settle(A.g, A.f, r, *gc);
+          gather_bounds(A.g, *gc);
+        }
         gather_interp(A.g, r, z[1], isg, *gc, D, B);
       }
     }
@@ -707,33 +711,26 @@ void k_push_explicit(PushArgs A) {
       }
     }
   }
-  // append the rejected particles to the implicit queue: wave ballots, one
-  // block total, one atomic on the block's queue segment
-  __shared__ unsigned s_off[kPushBlock / 64], s_base;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  unsigned long long mask = __ballot(enq);
-  if (lane == 0) s_off[wave] = (unsigned)__popcll(mask);
-  __syncthreads();
-  const unsigned seg = blockIdx.x % kQueueSegs;
-  if (threadIdx.x == 0) {
-    unsigned tot = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      unsigned c = s_off[w];
-      s_off[w] = tot;
-      tot += c;
-    }
-    s_base = tot ? atomicAdd(&A.st->seg_count[seg], tot) : 0u;
-  }
-  __syncthreads();
-  if (enq) {
-    unsigned slot = seg * A.seg_cap + s_base + s_off[wave] +
-                    (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-    A.queue[slot] = (int)kg;
-    // first iterate (RK4 result; the base of the learned guess in the hybrid)
-    if (A.use_gz && (A.guess == GRPIC_GUESS_RK4 || A.pusher == GRPIC_PUSH_HYB1 ||
-                     A.pusher == GRPIC_PUSH_HYB2)) {
+  // append the rejected particles to the implicit queue: one ballot and, when
+  // a lane was rejected, one atomic on the block's queue segment
+  static_assert(kPushBlock == 64, "the explicit push runs one wave per block");
+  const int lane = threadIdx.x & 63;
+  const unsigned long long mask = __ballot(enq);
+  if (mask != 0ull) {
+    const unsigned seg = blockIdx.x % kQueueSegs;
+    unsigned base = 0u;
+    if (lane == 0) base = atomicAdd(&A.st->seg_count[seg], (unsigned)__popcll(mask));
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (enq) {
+      const unsigned slot = seg * A.seg_cap + base +
+                            (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+      A.queue[slot] = (int)kg;
+      // first iterate (RK4 result; the base of the learned guess in the hybrid)
+      if (A.use_gz && (A.guess == GRPIC_GUESS_RK4 || A.pusher == GRPIC_PUSH_HYB1 ||
+                       A.pusher == GRPIC_PUSH_HYB2)) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
+        for (int i = 0; i < 6; ++i) A.gz[i][slot] = trial[i];
+      }
     }
   }
 }
@@ -891,10 +888,11 @@ static PushArgs make_args(grpic_ctx* c) {
 
 template <bool GRID, bool EVOLVE>
 static void push_impl(grpic_ctx* c, const PushArgs& A) {
-  // one wave per block: a block ends with a barrier and one returning atomic
-  // (the queue append), which with four waves per block held all four until
-  // the slowest was done (12.39 ms per C5 step at 256 threads, 11.95 at 128,
-  // 11.49 at 64); a one-wave block frees its slot as soon as it is done
+  // one wave per block: a block ends with the queue append (one returning
+  // atomic), which with four waves per block and a barrier held all four
+  // until the slowest was done (12.39 ms per C5 step at 256 threads, 11.95
+  // at 128, 11.49 at 64); a one-wave block frees its slot as soon as it is
+  // done, and its append needs no barrier
   const int block = kPushBlock;
   hipEvent_t ev;
   time_begin(c, GRPIC_K_PUSH, &ev);
