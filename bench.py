@@ -46,19 +46,21 @@ FLOP_KERNEL_RK4_GRID = 4 * (89 + 76 + 93) + 90
 FLOP_KERNEL_WEIGHTS = 610
 # algorithmic HBM bytes per particle of the explicit push pass of a charged
 # particle under Hyb2: state in/out (2 x 48), q/m, flags in/out, herr out,
-# iterations, old position + dphi, new weights (three stored, the fourth is
-# their complement) + cell (a neutral particle also reads H0, Hyb1 herr)
-BYTES_PUSH = 48 + 1 + 1 + 48 + 1 + 8 + 1 + 24 + 24 + 4
-# deposit per particle: old/new weights (three each) and cells, q/m, w, dphi,
-# flags
-BYTES_DEPOSIT = 24 + 24 + 4 + 4 + 1 + 8 + 8 + 1
+# iterations, old position + dphi, new weights (three stored in 4 B fixed
+# point, the fourth is their complement) + cell (a neutral particle also
+# reads H0, Hyb1 herr)
+BYTES_PUSH = 48 + 1 + 1 + 48 + 1 + 8 + 1 + 24 + 12 + 4
+# deposit per particle: old/new weights (three each, 4 B fixed point) and
+# cells, q/m, w, dphi, flags
+BYTES_DEPOSIT = 12 + 12 + 4 + 4 + 1 + 8 + 8 + 1
 # one launch of the Maxwell group (sub-steps 1-4, or 7-10) per cell: about 65
 # FP32 arrays read or written (two constitutive updates with their metric
 # coefficient tables and two curl updates)
 BYTES_FIELDS_PER_CELL = 65 * 4
 # the paper's current (deposit mode "paper"), per particle: r, theta, u_r,
-# u_theta, u_phi, w (FP64), q/m and flags, node weights W1..W3 and cell
-BYTES_DEPOSIT_PAPER = 6 * 8 + 1 + 1 + 24 + 4
+# u_theta, u_phi, w (FP64), q/m and flags, node weights W1..W3 (4 B fixed
+# point) and cell
+BYTES_DEPOSIT_PAPER = 6 * 8 + 1 + 1 + 12 + 4
 # divergence cleaning, per node and chain: every Jacobi sweep reads phi, the
 # source and the two face coefficients and writes phi (5 x 8 B); the source
 # and correction kernels about 100 B more

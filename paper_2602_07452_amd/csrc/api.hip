@@ -140,11 +140,11 @@ void alloc_particles(grpic_ctx* c, long cap) {
     V->id = dalloc<uint32_t>(n);
     bool grid = c->cfg.field_mode != GRPIC_FIELDS_NONE;
     // weights of nodes 1..3; node 0's is the complement 1 - W1 - W2 - W3
-    for (int q = 1; q < 4; ++q) V->W[q] = grid ? dalloc<double>(n) : nullptr;
+    for (int q = 1; q < 4; ++q) V->W[q] = grid ? dalloc<uint32_t>(n) : nullptr;
     V->cell = grid ? dalloc<int>(n) : nullptr;
   }
   bool evolve = c->cfg.field_mode == GRPIC_FIELDS_EVOLVE;
-  for (int q = 1; q < 4; ++q) P.Wn[q] = evolve ? dalloc<double>(n) : nullptr;
+  for (int q = 1; q < 4; ++q) P.Wn[q] = evolve ? dalloc<uint32_t>(n) : nullptr;
   P.celln = evolve ? dalloc<int>(n) : nullptr;
   P.r_old = evolve ? dalloc<double>(n) : nullptr;
   P.th_old = evolve ? dalloc<double>(n) : nullptr;
@@ -1384,7 +1384,7 @@ std::vector<StateItem> state_items(grpic_ctx* c, long n) {
   v.push_back({P.iters, (size_t)n});
   v.push_back({P.id, sizeof(uint32_t) * (size_t)n});
   if (P.cell) {
-    for (int q = 1; q < 4; ++q) v.push_back({P.W[q], d});
+    for (int q = 1; q < 4; ++q) v.push_back({P.W[q], sizeof(uint32_t) * (size_t)n});
     v.push_back({P.cell, sizeof(int) * (size_t)n});
   }
   if (P.t) v.push_back({P.t, d});

@@ -123,7 +123,8 @@ __device__ __forceinline__ void cell_flux(const Sink& S, double s, int p, int q,
 // waits for them until the record is used (the loads of the next records
 // stay in flight meanwhile)
 struct PRec {
-  double W1, W2, W3, N1, N2, N3, dphi, w;
+  double dphi, w;
+  uint32_t W1, W2, W3, N1, N2, N3;  // fixed-point weights (wq_decode)
   int c0, c1;
   uint8_t fl;
   int8_t qm;
@@ -153,12 +154,12 @@ struct PDep {
 };
 
 __device__ __forceinline__ void unpack_rec(const PRec& r, PDep& d) {
-  d.Wo[1] = r.W1;
-  d.Wo[2] = r.W2;
-  d.Wo[3] = r.W3;
-  d.Wn[1] = r.N1;
-  d.Wn[2] = r.N2;
-  d.Wn[3] = r.N3;
+  d.Wo[1] = wq_decode(r.W1);
+  d.Wo[2] = wq_decode(r.W2);
+  d.Wo[3] = wq_decode(r.W3);
+  d.Wn[1] = wq_decode(r.N1);
+  d.Wn[2] = wq_decode(r.N2);
+  d.Wn[3] = wq_decode(r.N3);
   d.Wo[0] = 1.0 - d.Wo[1] - d.Wo[2] - d.Wo[3];
   d.Wn[0] = 1.0 - d.Wn[1] - d.Wn[2] - d.Wn[3];
   d.dphi = r.dphi;
@@ -209,8 +210,8 @@ __device__ __forceinline__ void load_xrec(const DepArgs& A, long k, XRec& x) {
   const ParticleView& P = A.p;
 #pragma unroll
   for (int c = 1; c < 4; ++c) {
-    x.Wo[c] = P.W[c][k];
-    x.Wn[c] = P.Wn[c][k];
+    x.Wo[c] = wq_decode(P.W[c][k]);
+    x.Wn[c] = wq_decode(P.Wn[c][k]);
   }
   x.r0 = P.r_old[k];
   x.t0 = P.th_old[k];
@@ -529,7 +530,9 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     long nn = (long)(q0 + (c >> 1)) * (A.nr + 1) + p0 + (c & 1);
-    const double wc = c ? P.W[c][k] : 1.0 - P.W[1][k] - P.W[2][k] - P.W[3][k];
+    const double w1 = wq_decode(P.W[1][k]), w2 = wq_decode(P.W[2][k]),
+                 w3 = wq_decode(P.W[3][k]);
+    const double wc = c == 0 ? 1.0 - w1 - w2 - w3 : (c == 1 ? w1 : (c == 2 ? w2 : w3));
     long long q = llrint(qw * wc * A.acc.scale);
     if (q != 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(A.acc.Q + nn),
@@ -548,8 +551,8 @@ __global__ __launch_bounds__(256) void k_deposit_rho(DepArgs A) {
 // accumulated are the finalize kernel's units: charge for rho, charge times
 // dt (and over the subgrid spacing for J^r, J^theta) for the currents.
 template <class Sink>
-__device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const double* W1,
-                               const double* W2, const double* W3, const int* cell,
+__device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const uint32_t* W1,
+                               const uint32_t* W2, const uint32_t* W3, const int* cell,
                                double dt) {
   const ParticleView& P = A.p;
   const GridView& g = A.g;
@@ -568,7 +571,7 @@ __device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const do
   split_cell(A, cell[k], p, q);
   // rho and J^phi on the nodes
   {
-    const double w1 = W1[k], w2 = W2[k], w3 = W3[k];
+    const double w1 = wq_decode(W1[k]), w2 = wq_decode(W2[k]), w3 = wq_decode(W3[k]);
     const double W[4] = {1.0 - w1 - w2 - w3, w1, w2, w3};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -616,9 +619,9 @@ __device__ void paper_particle(const DepArgs& A, const Sink& S, long k, const do
 // (widened one node down, where the half-subgrid cells start) is summed in
 // LDS and flushed with one global atomic per touched entry; a chunk whose
 // box does not fit goes to global atomics directly
-__global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const double* W1,
-                                                             const double* W2,
-                                                             const double* W3,
+__global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const uint32_t* W1,
+                                                             const uint32_t* W2,
+                                                             const uint32_t* W3,
                                                              const int* cell, double dt) {
   __shared__ long long bins[4 * kDepBins];
   __shared__ int box[4];
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit_paper(DepArgs A, const do
   }
 }
 
-static void launch_deposit_paper(grpic_ctx* c, const double* const* W, const int* cell) {
+static void launch_deposit_paper(grpic_ctx* c, const uint32_t* const* W, const int* cell) {
   DepArgs A;
   A.g = make_grid_view(c);
   A.p = c->pv;
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(256) void k_weights(GridView g, ParticleView P) {
   double W[4];
   dep_weights(g, r, th, p, q, W);
 #pragma unroll
-  for (int c = 1; c < 4; ++c) P.W[c][k] = W[c];
+  for (int c = 1; c < 4; ++c) P.W[c][k] = wq_encode(W[c]);
   P.cell[k] = q * g.nr + p;
 }
 

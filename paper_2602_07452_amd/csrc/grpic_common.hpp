@@ -23,11 +23,12 @@ struct ParticleView {
   int8_t* qm;                            // q/m in {+1, -1, 0}
   uint8_t *flags, *iters;
   uint32_t* id;
-  // deposit weights of the cell's nodes 1..3 at x (W[0] unused: node 0's
-  // weight is 1 - W1 - W2 - W3, so the four sum to one to FP64 rounding)
-  double* W[4];
+  // deposit weights of the cell's nodes 1..3 at x, stored in 31-bit fixed
+  // point (wq_encode / wq_decode; W[0] unused: node 0's weight is
+  // 1 - W1 - W2 - W3 of the decoded values, so the four sum to one)
+  uint32_t* W[4];
   int* cell;                             // node cell index q * nr + p
-  double* Wn[4];                         // the same at the pushed position
+  uint32_t* Wn[4];                       // the same at the pushed position
   int* celln;
   double *r_old, *th_old, *dphi;         // previous position, phi change
   double* t;                             // own time (field mode NONE only)
@@ -59,6 +60,18 @@ struct Stats {
   unsigned int cross_count;      // crossing moves queued by the deposit
   unsigned long long deposit_outside;  // particles outside their planned box
 };
+
+// Stored deposit weights: W in [0, 1] as round(W 2^31) in a uint32 (an
+// absolute error below 2^-32, 2^7 below the FP32 rounding of the densities
+// and currents they make, and half the bytes of an FP64 weight).  Every
+// user decodes the same stored values, so charge conservation, which needs
+// the deposit's old and new weights to be the ones rho was made of, holds
+// exactly.
+constexpr double kWScale = 2147483648.0;  // 2^31
+__device__ __forceinline__ uint32_t wq_encode(double w) {
+  return (uint32_t)__double2uint_rn(fmin(fmax(w, 0.0), 1.0) * kWScale);
+}
+__device__ __forceinline__ double wq_decode(uint32_t q) { return (double)q * (1.0 / kWScale); }
 
 // fixed-point charge accumulators (int64, deterministic under atomics)
 struct DepositAcc {

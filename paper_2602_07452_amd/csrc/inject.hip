@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_inj_write(InjArgs A) {
     P.iters[slot] = 0;
     P.id[slot] = (uint32_t)slot;
 #pragma unroll
-    for (int i = 1; i < 4; ++i) P.W[i][slot] = W[i];
+    for (int i = 1; i < 4; ++i) P.W[i][slot] = wq_encode(W[i]);
     P.cell[slot] = cq * nr + cp;
   }
   atomicMax(A.wmax, (unsigned long long)__double_as_longlong(w));

@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
         d[u] = base[key] + atomicAdd(&hist[key], 1);
       }
     }
-    double x[U][12];
+    double x[U][9];
+    uint32_t wq[U][3];
     int8_t qm[U];
     uint8_t fl[U], it[U];
     uint32_t id[U];
@@ -218,9 +219,9 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
       x[u][6] = S.H0[k];
       x[u][7] = S.herr[k];
       x[u][8] = S.w[k];
-      x[u][9] = S.W[1][k];
-      x[u][10] = S.W[2][k];
-      x[u][11] = S.W[3][k];
+      wq[u][0] = S.W[1][k];
+      wq[u][1] = S.W[2][k];
+      wq[u][2] = S.W[3][k];
       qm[u] = S.qm[k];
       fl[u] = S.flags[k];
       it[u] = S.iters[k];
@@ -240,9 +241,9 @@ __global__ __launch_bounds__(256) void k_tile_scatter(SortArgs A) {
       D.H0[t] = x[u][6];
       D.herr[t] = x[u][7];
       D.w[t] = x[u][8];
-      D.W[1][t] = x[u][9];
-      D.W[2][t] = x[u][10];
-      D.W[3][t] = x[u][11];
+      D.W[1][t] = wq[u][0];
+      D.W[2][t] = wq[u][1];
+      D.W[3][t] = wq[u][2];
       D.qm[t] = qm[u];
       D.flags[t] = fl[u];
       D.iters[t] = it[u];

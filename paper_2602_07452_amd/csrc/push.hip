@@ -160,7 +160,10 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   const double Ur = (a2 * s2 * irho2 + ixi) * ur + irp * up;
   const double Ut = irho2 * ut;
   const double Up = irp * ur + irho2 * is2 * up;
-  const double G2 = 1.0 + ur * Ur + ut * Ut + up * Up;
+  // u_i gamma^ij u_j = Aq / rho2 + u_r^2 / xi, with Aq = a^2 s2 u_r^2 + u_th^2
+  // + u_ph^2 / s2 + 2 a u_r u_ph the quadratic form of the gravity terms
+  const double q = ur * Ur + ut * Ut + up * Up;
+  const double G2 = 1.0 + q;
   const double iG = frsq(G2), G = G2 * iG;  // 1/Gamma and Gamma
   const double aiG = alpha * iG;
   if (e) *e = alpha * G - betar * ur;
@@ -169,13 +172,13 @@ __device__ __forceinline__ void eval(const PushArgs& A, double qm,
   f[2] = aiG * Up;
   // gravity: -Gamma d_k alpha + u_r d_k beta^r - alpha/(2 Gamma) u u d_k gamma^-1
   const double i4 = irho2 * irho2, ixi2 = ixi * ixi, ur2 = ur * ur;
-  const double Aq = a2 * s2 * ur2 + ut * ut + up * up * is2 + 2.0 * a * ur * up;
+  const double Aq_r = fma(-ixi, ur2, q);  // Aq / rho2, from the sum above
   const double Bq = irho2 * (a2 * ur2 - up * up * is2 * is2);
   const double Cq = 0.5 * G * alpha * ixi + ur * ixi2 + 0.5 * aiG * ixi2 * ur2;
   const double dxr = 2.0 * irho2 * (1.0 - 2.0 * r * r * irho2);  // d_r xi
   const double dxt = 4.0 * r * a2 * sc * i4;                      // d_theta xi
-  const double gr = dxr * Cq + aiG * r * i4 * Aq;
-  const double gt = dxt * Cq - aiG * sc * (a2 * i4 * Aq + Bq);
+  const double gr = dxr * Cq + aiG * r * irho2 * Aq_r;
+  const double gt = dxt * Cq - aiG * sc * (a2 * irho2 * Aq_r + Bq);
   if constexpr (CACHE) {
     if (charged) {
       if constexpr (COEFS) {
@@ -627,7 +630,7 @@ __device__ void finalize(const PushArgs& A, Ix k, const double* z,
       if (moved) sincos_near(out[1], z[1], s0, c0, &st, &ct);
       cell_and_weights(A.g, out[0], out[1], st, ct, p, q, W, hint);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) at(P.Wn[c], k) = W[c];
+      for (int c = 1; c < 4; ++c) at(P.Wn[c], k) = wq_encode(W[c]);
       at(P.celln, k) = q * A.g.nr + p;
     }
   }
