@@ -316,8 +316,8 @@ struct GatherLoads {
   double rn0, rn1, irn, rh0, rh1, irh;
   // theta_node(qn), theta_node(qn + 1), theta_half(qn), theta_half(qh)
   double tn0, tn1, thq, thh;
-  // with gather_bounds: the point lies in all four cells (node and half, in
-  // r and in theta) exactly when rlo <= r < rhi and tlo <= th < thi
+  // with gather_bounds: a point with rlo <= r < rhi and tlo <= th < thi lies
+  // in all four cells (node and half, in r and in theta)
   double rlo, rhi, tlo, thi;
   int pn, ph, qn, qh;
   // with gather_coefs: each component's corners v_ij (i radial, j angular)
