@@ -280,15 +280,16 @@ __device__ __forceinline__ void rk4(const PushArgs& A, double dt, double qm,
   *Wq = c6 * (pacc + p);
 }
 
+// max_i |zn_i - zo_i| / max(|zn_i|, 1) <= tol, tested without divisions as
+// |zn_i - zo_i| <= tol max(|zn_i|, 1) for every i (the two differ only when
+// a term lies within rounding of tol); a NaN term passes, as it does not
+// raise that maximum
 __device__ __forceinline__ bool small_change(const double* zn, const double* zo,
                                              double tol) {
-  double m = 0.0;
+  bool ok = true;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double sc = fmax(fabs(zn[i]), 1.0);
-    m = fmax(m, fabs(zn[i] - zo[i]) / sc);
-  }
-  return m <= tol;
+  for (int i = 0; i < 6; ++i) ok = ok & !(fabs(zn[i] - zo[i]) > tol * fmax(fabs(zn[i]), 1.0));
+  return ok;
 }
 
 // implicit midpoint rule by fixed-point iteration; zk: guess in, result out.
