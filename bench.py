@@ -46,13 +46,13 @@ FLOP_KERNEL_RK4_GRID = 4 * (89 + 76 + 93) + 90
 FLOP_KERNEL_WEIGHTS = 610
 # algorithmic HBM bytes per particle of the explicit push pass of a charged
 # particle under Hyb2: state in/out (2 x 48), q/m, flags in/out, herr out,
-# iterations, old position + dphi, new weights (three stored in 4 B fixed
-# point, the fourth is their complement) + cell (a neutral particle also
-# reads H0, Hyb1 herr)
-BYTES_PUSH = 48 + 1 + 1 + 48 + 1 + 8 + 1 + 24 + 12 + 4
+# iterations, old position (2 x 8) + dphi (FP32), new weights (three
+# stored in 4 B fixed point, the fourth is their complement) + cell (a
+# neutral particle also reads H0, Hyb1 herr)
+BYTES_PUSH = 48 + 1 + 1 + 48 + 1 + 8 + 1 + 20 + 12 + 4
 # deposit per particle: old/new weights (three each, 4 B fixed point) and
-# cells, q/m, w, dphi, flags
-BYTES_DEPOSIT = 12 + 12 + 4 + 4 + 1 + 8 + 8 + 1
+# cells, q/m, w, dphi (FP32), flags
+BYTES_DEPOSIT = 12 + 12 + 4 + 4 + 1 + 8 + 4 + 1
 # one launch of the Maxwell group (sub-steps 1-4, or 7-10) per cell: about 65
 # FP32 arrays read or written (two constitutive updates with their metric
 # coefficient tables and two curl updates)

@@ -148,7 +148,7 @@ void alloc_particles(grpic_ctx* c, long cap) {
   P.celln = evolve ? dalloc<int>(n) : nullptr;
   P.r_old = evolve ? dalloc<double>(n) : nullptr;
   P.th_old = evolve ? dalloc<double>(n) : nullptr;
-  P.dphi = evolve ? dalloc<double>(n) : nullptr;
+  P.dphi = evolve ? dalloc<float>(n) : nullptr;
   c->xqueue = evolve ? dalloc<int>(n) : nullptr;
   P.t = c->cfg.field_mode == GRPIC_FIELDS_NONE ? dalloc<double>(n) : nullptr;
   if (c->cfg.pusher != GRPIC_PUSH_RK4) {

@@ -123,7 +123,8 @@ __device__ __forceinline__ void cell_flux(const Sink& S, double s, int p, int q,
 // waits for them until the record is used (the loads of the next records
 // stay in flight meanwhile)
 struct PRec {
-  double dphi, w;
+  double w;
+  float dphi;
   uint32_t W1, W2, W3, N1, N2, N3;  // fixed-point weights (wq_decode)
   int c0, c1;
   uint8_t fl;
@@ -162,7 +163,7 @@ __device__ __forceinline__ void unpack_rec(const PRec& r, PDep& d) {
   d.Wn[3] = wq_decode(r.N3);
   d.Wo[0] = 1.0 - d.Wo[1] - d.Wo[2] - d.Wo[3];
   d.Wn[0] = 1.0 - d.Wn[1] - d.Wn[2] - d.Wn[3];
-  d.dphi = r.dphi;
+  d.dphi = (double)r.dphi;
   d.c0 = r.c0;
   d.c1 = r.c1;
   d.qw = (double)r.qm * r.w;

@@ -30,7 +30,8 @@ struct ParticleView {
   int* cell;                             // node cell index q * nr + p
   uint32_t* Wn[4];                       // the same at the pushed position
   int* celln;
-  double *r_old, *th_old, *dphi;         // previous position, phi change
+  double *r_old, *th_old;                // previous position
+  float* dphi;  // phi change of the step (FP32: it only scales J^phi, an FP32 output)
   double* t;                             // own time (field mode NONE only)
 };
 

@@ -624,7 +624,7 @@ __device__ void finalize(const PushArgs& A, Ix k, const double* z,
   if (EVOLVE) {
     at(P.r_old, k) = z[0];
     at(P.th_old, k) = z[1];
-    at(P.dphi, k) = out[2] - z[2];
+    at(P.dphi, k) = (float)(out[2] - z[2]);
     if (fl & F_ALIVE) {
       int p, q;
       double W[4], st = sn, ct = cn;
