@@ -275,15 +275,16 @@ int grpic_sample_particles(grpic_ctx *ctx, long m, const long *ids,
  * each of its own shape) when the context has a grid, then the particles in
  * storage order (r, theta, phi, u_r, u_theta, u_phi, H0, herr, w as FP64;
  * q/m as int8; flags, iters as uint8; id as uint32; with a grid the
- * deposit weights W1..W3 of the current position as FP64 and the cell
- * index as int32; without a grid the particle times as FP64), then the
+ * deposit weights W1..W3 of the current position as uint32 fixed point
+ * (round(W 2^31)) and the cell index as int32; without a grid the
+ * particle times as FP64), then the
  * diagnostic counters.  Restoring it into a
  * context of the same grid, field mode and dt continues the run exactly as
  * the uninterrupted one (the deposit sums are order-independent).  The
  * learned-guess network is not part of it (grpic_mlp_get / grpic_mlp_set). */
 typedef struct grpic_state_header {
   char magic[8];          /* "GRPICST" and a zero byte                      */
-  int32_t version;        /* 1                                              */
+  int32_t version;        /* 2                                              */
   int32_t field_mode;     /* enum grpic_field_mode                          */
   int32_t nr, nth;        /* grid cells                                     */
   double a, r_in, r_out, theta0, dt;

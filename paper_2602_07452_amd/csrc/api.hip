@@ -1421,7 +1421,7 @@ int grpic_get_state(grpic_ctx* c, void* host, size_t bytes) {
     if (bytes < need) throw Error(GRPIC_E_INVALID, "buffer smaller than the snapshot");
     grpic_state_header h{};
     std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
-    h.version = 1;
+    h.version = 2;
     h.field_mode = c->cfg.field_mode;
     h.nr = c->nr;
     h.nth = c->nth;
@@ -1453,7 +1453,7 @@ int grpic_set_state(grpic_ctx* c, const void* host, size_t bytes) {
     grpic_state_header h;
     if (bytes < sizeof(h)) throw Error(GRPIC_E_INVALID, "block shorter than a snapshot header");
     std::memcpy(&h, host, sizeof(h));
-    if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0 || h.version != 2)
       throw Error(GRPIC_E_INVALID, "not a snapshot of this library");
     if (h.field_mode != c->cfg.field_mode || h.nr != c->nr || h.nth != c->nth ||
         h.a != c->cfg.a || h.dt != c->cfg.dt ||

@@ -52,7 +52,7 @@ def _resume_matches(cfg, setup, before=4, after=5, graph=False):
         ctx.step(after)
         want = _everything(ctx)
     h = G.state_header(snap)
-    assert h.magic == b"GRPICST" and h.version == 1 and h.bytes == snap.size
+    assert h.magic == b"GRPICST" and h.version == 2 and h.bytes == snap.size
     assert h.steps == before and h.n == n
     with G.Context(cfg) as ctx:
         ctx.set_state(snap)
